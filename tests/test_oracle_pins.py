@@ -1,0 +1,424 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each checks a closed form, an invariance,
+an identity the paper states, or a textbook special case, so that a dropped term, a
+wrong sign or index, or a transposed operand anywhere in the oracle fails one of them.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_09621_amd import inputs as IN
+
+M0 = 1.3
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+@pytest.fixture(scope="module")
+def D(oracle_lib):
+    from oracle import dense
+    return dense
+
+
+def rand_field(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def lat(O, dims, eps=0.5, seed=11, Ns=4, tbc=-1):
+    U = IN.gauge_links(dims, eps, seed)
+    return O.Lattice(dims, U, m0=M0, omega=IN.optimal_omega(Ns), tbc=tbc)
+
+
+# ----------------------------------------------------------------- gamma basis
+
+def test_gamma_clifford_and_chiral(O):
+    g = [O.gamma(mu) for mu in range(5)]
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T)
+        for b in range(4):
+            assert np.allclose(g[a] @ g[b] + g[b] @ g[a], 2 * (a == b) * np.eye(4), atol=1e-15)
+    # chiral basis: gamma_5 = diag(1, 1, -1, -1), so P_+ is the upper two spins (Eq.(DTm1m2) blocks)
+    assert np.allclose(g[4], np.diag([1, 1, -1, -1]))
+
+
+# ----------------------------------------------------------------- Wilson D_w
+
+@pytest.mark.parametrize("tbc", [-1, 1])
+def test_dw_free_field_plane_wave(O, D, tbc):
+    """U = 1: D_w e^{ipx} chi = [(4 - m0 - sum cos p) + i sum gamma sin p] e^{ipx} chi."""
+    dims = (4, 4, 2, 6)
+    L = O.Lattice(dims, IN.unit_links(dims), m0=M0, tbc=tbc)
+    rng = np.random.default_rng(3)
+    Lx, Ly, Lz, Lt = dims
+    t, z, y, x = np.indices((Lt, Lz, Ly, Lx))
+    for _ in range(4):
+        n = rng.integers(0, 8, size=4)
+        shift_t = 0.5 if tbc < 0 else 0.0
+        p = 2 * np.pi * np.array([n[0] / Lx, n[1] / Ly, n[2] / Lz, (n[3] + shift_t) / Lt])
+        chi = rand_field((4, 3), int(n.sum()))
+        ph = np.exp(1j * (p[0] * x + p[1] * y + p[2] * z + p[3] * t))
+        psi = ph[..., None, None] * chi
+        expect = ph[..., None, None] * np.einsum("ab,bc->ac", D.free_dw_momentum(p, M0), chi)
+        assert np.abs(L.dw(psi) - expect).max() < 1e-13
+
+
+def test_dw_gamma5_hermiticity(O):
+    L = lat(O, (4, 2, 2, 4))
+    x, y = rand_field(L.shape4, 1), rand_field(L.shape4, 2)
+    g5 = O.gamma(4)
+    # <y, D_w x> = <D_w^dagger y, x> and D_w^dagger = gamma_5 D_w gamma_5
+    lhs = np.vdot(y, L.dw(x))
+    rhs = np.vdot(L.dw(y, dag=True), x)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    g5y = np.einsum("ab,...bc->...ac", g5, y)
+    assert np.abs(np.einsum("ab,...bc->...ac", g5, L.dw(g5y)) - L.dw(y, dag=True)).max() < 1e-13
+
+
+def test_dw_gauge_covariance(O):
+    """D_w[U^g] (g psi) = g D_w[U] psi with U^g_mu(x) = g(x) U_mu(x) g(x+mu)^dagger."""
+    dims = (4, 2, 4, 2)
+    L = lat(O, dims)
+    Lx, Ly, Lz, Lt = dims
+    g = IN.random_su3(L.V, 5).reshape(Lt, Lz, Ly, Lx, 3, 3)
+    U = L.U
+    Ug = np.empty_like(U)
+    axes = {0: 3, 1: 2, 2: 1, 3: 0}
+    for mu in range(4):
+        gf = np.roll(g, -1, axis=axes[mu])
+        Ug[..., mu, :, :] = g @ U[..., mu, :, :] @ np.conj(np.swapaxes(gf, -1, -2))
+    Lg = O.Lattice(dims, Ug, m0=M0, tbc=-1)
+    psi = rand_field(L.shape4, 9)
+    gpsi = np.einsum("...ij,...aj->...ai", g, psi)
+    lhs = Lg.dw(gpsi)
+    rhs = np.einsum("...ij,...aj->...ai", g, L.dw(psi))
+    assert np.abs(lhs - rhs).max() < 1e-13
+
+
+# ----------------------------------------------------------------- s-space
+
+def test_mpm_transpose_and_reflection(O):
+    L = lat(O, (2, 2, 2, 2), Ns=8)
+    R5 = np.eye(8)[::-1]
+    for m in (0.01, 0.3, 1.0):
+        Mp, Mm = L.mpm(m, +1), L.mpm(m, -1)
+        assert np.abs(Mm - Mp.T).max() < 1e-14
+        assert np.abs(R5 @ Mp @ R5 - Mm).max() < 1e-13
+    # at m = 1 the domain wall closes into a ring: M_+(1) is antisymmetric in the rescaled basis
+    w = np.sqrt(L.omega)
+    A = w[:, None] * L.mpm(1.0, +1) * w[None, :]
+    assert np.abs(A + A.T).max() < 1e-13
+
+
+@pytest.mark.parametrize("Ns", [4, 8, 16])
+def test_delta_rank_one_closed_form(O, Ns):
+    """Eqs.(delta_ij)-(k_ij): R5 (M(mj) - M(mi)) = k Om Om^T, the same Om for both chiralities,
+    with k = 2 (mj - mi) / ((1 + mj)(1 + mi)) (c = 1, lambda = 0) and Om_s = (-1)^s omega_s^{-1/2}."""
+    L = lat(O, (2, 2, 2, 2), Ns=Ns)
+    Om_cf = np.array([(-1) ** s for s in range(1, Ns + 1)]) / np.sqrt(L.omega)
+    for mj, mi in [(1.0, 0.01), (0.1, 0.005), (0.55, 0.1), (0.3, 0.3)]:
+        kcf = 2 * (mj - mi) / ((1 + mj) * (1 + mi))
+        for chir in (+1, -1):
+            k, Om, rem = L.k_omega(mj, mi, chir)
+            assert rem < 1e-12
+            assert np.abs(k * np.outer(Om, Om) - kcf * np.outer(Om_cf, Om_cf)).max() < 1e-12 * max(1, abs(kcf))
+
+
+# ----------------------------------------------------------------- 5D operators
+
+def test_dt_from_odwf(O):
+    """D_odwf = omega^{1/2} D_T omega^{1/2} (1 + L), the relation between the optimal-DWF operator
+    and D_T of Eq.(DTm1m2) (checked on random fields)."""
+    L = lat(O, (2, 2, 2, 4), Ns=6)
+    psi = rand_field(L.shape5, 4)
+    mp, mm = 0.05, 0.3
+    Ns = L.Ns
+    # (1 + L) psi with L = P_+ L_+(m+) + P_- L_-(m-): written as an explicit shift here
+    lp = np.roll(psi, 1, axis=0)
+    lp[0] *= -mp
+    lm = np.roll(psi, -1, axis=0)
+    lm[Ns - 1] *= -mm
+    onel = psi.copy()
+    onel[..., :2, :] += lp[..., :2, :]
+    onel[..., 2:, :] += lm[..., 2:, :]
+    w = np.sqrt(L.omega)[:, None, None, None, None, None, None]
+    rhs = w * L.dt(w * onel, mp, mm)
+    assert np.abs(L.dodwf(psi, mp, mm) - rhs).max() < 1e-12
+
+
+@pytest.mark.parametrize("mp,mm", [(0.05, 0.05), (0.01, 0.3), (1.0, 0.1)])
+def test_ht_hermitian(O, mp, mm):
+    L = lat(O, (2, 4, 2, 2), Ns=8)
+    x, y = rand_field(L.shape5, 1), rand_field(L.shape5, 2)
+    a = np.vdot(y, L.ht(x, mp, mm))
+    b = np.vdot(L.ht(y, mp, mm), x)
+    assert abs(a - b) < 1e-12 * abs(a)
+    # adjoint consistency of D_T and D_T^dagger
+    a = np.vdot(y, L.dt(x, mp, mm))
+    b = np.vdot(L.dt(y, mp, mm, dag=True), x)
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+def test_odwf_adjoint(O):
+    L = lat(O, (2, 2, 4, 2), Ns=4)
+    x, y = rand_field(L.shape5, 5), rand_field(L.shape5, 6)
+    a = np.vdot(y, L.dodwf(x, 0.1, 0.02))
+    b = np.vdot(L.dodwf(y, 0.1, 0.02, dag=True), x)
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+def test_dt_gauge_covariance(O):
+    dims = (2, 2, 2, 4)
+    L = lat(O, dims, Ns=4)
+    Lx, Ly, Lz, Lt = dims
+    g = IN.random_su3(L.V, 8).reshape(Lt, Lz, Ly, Lx, 3, 3)
+    axes = {0: 3, 1: 2, 2: 1, 3: 0}
+    Ug = np.empty_like(L.U)
+    for mu in range(4):
+        gf = np.roll(g, -1, axis=axes[mu])
+        Ug[..., mu, :, :] = g @ L.U[..., mu, :, :] @ np.conj(np.swapaxes(gf, -1, -2))
+    Lg = O.Lattice(dims, Ug, m0=M0, omega=L.omega)
+    psi = rand_field(L.shape5, 3)
+    gpsi = np.einsum("...ij,...aj->...ai", g, psi)
+    assert np.abs(Lg.dt(gpsi, 0.1, 0.2) - np.einsum("...ij,...aj->...ai", g, L.dt(psi, 0.1, 0.2))).max() < 1e-12
+
+
+def test_dt_at_matches_full(O):
+    L = lat(O, (4, 2, 2, 4), Ns=4)
+    psi = rand_field(L.shape5, 12)
+    full = L.dt(psi, 0.02, 0.7)
+    sites = np.array([0, 5, 17, L.V - 1])
+    part = L.dt_at(psi, 0.02, 0.7, sites)
+    ref = full.reshape(L.Ns, L.V, 4, 3)[:, sites].transpose(1, 0, 2, 3)
+    assert np.abs(part - ref).max() < 1e-13
+
+
+# ----------------------------------------------------------------- dense brute force on 2^4
+
+@pytest.fixture(scope="module")
+def tiny(O, D):
+    dims = (2, 2, 2, 2)
+    L = lat(O, dims, eps=0.6, seed=21, Ns=4)
+    sh = L.shape5
+    cache = {}
+
+    def HT(mp, mm):
+        key = ("H", mp, mm)
+        if key not in cache:
+            cache[key] = D.dense(lambda v: L.ht(v, mp, mm), sh)
+        return cache[key]
+
+    def DT(mp, mm):
+        key = ("D", mp, mm)
+        if key not in cache:
+            cache[key] = D.dense(lambda v: L.dt(v, mp, mm), sh)
+        return cache[key]
+
+    return L, HT, DT
+
+
+def dense_action(O, D, L, HT, chir, m3, m4, mo):
+    """Dense matrix of one chiral action of Eqs.(m1m2_m1m4)/(m1m2_m3m2) from the oracle's
+    dense H_T and its rank-one factor k Om Om^T."""
+    Pp, Pm = D.chiral_projectors(L.V)
+    if chir < 0:
+        k, Om, _ = L.k_omega(mo, m4, -1)
+        P = Pm
+    else:
+        k, Om, _ = L.k_omega(mo, m3, +1)
+        P = Pp
+    E = D.omega_embed(L, Om)
+    Hi = np.linalg.inv(HT(m3, m4))
+    return P @ (np.eye(L.V * 12) + chir * k * E.T @ Hi @ E) @ P, P
+
+
+@pytest.mark.parametrize("m3,m4,mo", [(0.05, 0.05, 0.3), (0.01, 0.1, 1.0), (0.1, 0.02, 0.5)])
+def test_det_minus_action(O, D, tiny, m3, m4, mo):
+    """Eq.(m1m2_m1m4): det P_-[1 - k(m2,m4) Om^T H_T(m3,m4)^{-1} Om]P_- = det D_T(m3,m2) / det D_T(m3,m4)."""
+    L, HT, DT = tiny
+    A, P = dense_action(O, D, L, HT, -1, m3, m4, mo)
+    la, ph = D.subspace_logdet(A, P)
+    target = D.logdet(DT(m3, mo))[0] - D.logdet(DT(m3, m4))[0]
+    assert abs(la - target) < 1e-10
+    assert abs(ph - 1) < 1e-12
+    assert np.abs(A - A.conj().T).max() < 1e-12
+
+
+@pytest.mark.parametrize("m3,m4,mo", [(0.05, 0.3, 0.3), (0.01, 0.1, 1.0), (0.2, 0.02, 0.6)])
+def test_det_plus_action(O, D, tiny, m3, m4, mo):
+    """Eq.(m1m2_m3m2): det P_+[1 + k(m1,m3) Om^T H_T(m3,m4)^{-1} Om]P_+ = det D_T(m1,m4) / det D_T(m3,m4)."""
+    L, HT, DT = tiny
+    A, P = dense_action(O, D, L, HT, +1, m3, m4, mo)
+    la, ph = D.subspace_logdet(A, P)
+    target = D.logdet(DT(mo, m4))[0] - D.logdet(DT(m3, m4))[0]
+    assert abs(la - target) < 1e-10
+    assert abs(ph - 1) < 1e-12
+
+
+def test_hinv_positive_definite_and_noMP(O, D, tiny):
+    """Eq.(Hij) as the sum of the chiral parts of Eq.(noMP): Hermitian positive definite and
+    det H^{-1}(M, m) = det D_T(M) / det D_T(m) (Eqs.(det_minus), (det_plus), (EOFA_noMP_D))."""
+    L, HT, DT = tiny
+    m, M = 0.02, 1.0
+    A1, _ = dense_action(O, D, L, HT, -1, m, m, M)
+    A2, _ = dense_action(O, D, L, HT, +1, m, M, M)
+    Hi = A1 + A2
+    assert np.abs(Hi - Hi.conj().T).max() < 1e-12
+    ev = np.linalg.eigvalsh(Hi)
+    assert ev.min() > 0.05
+    la = D.logdet(Hi)[0]
+    assert abs(la - (D.logdet(DT(M, M))[0] - D.logdet(DT(m, m))[0])) < 1e-9
+    # equal masses: H^{-1}(m, m) = I
+    B1, _ = dense_action(O, D, L, HT, -1, m, m, m)
+    B2, _ = dense_action(O, D, L, HT, +1, m, m, m)
+    assert np.abs(B1 + B2 - np.eye(L.V * 12)).max() < 1e-13
+
+
+def test_eq_H_plus_part(O, D, tiny):
+    """Eq.(H): H_T(1) - Delta_+(1, m) P_+ equals H_T(m, 1), which is how Eq.(Hij) reduces to Eq.(H)."""
+    L, HT, DT = tiny
+    m = 0.03
+    k, Om, _ = L.k_omega(1.0, m, +1)
+    Pp, _ = D.chiral_projectors(L.V, L.Ns)
+    Delta = np.kron(k * np.outer(Om, Om), np.eye(L.V * 12))
+    lhs = HT(1.0, 1.0) - Delta @ Pp
+    assert np.abs(lhs - HT(m, 1.0)).max() < 1e-12
+
+
+def test_new_mp_telescopes(O, D, tiny):
+    """Eq.(new_MP): (m,m)/(m,mh) * (m,mh)/(M,mh) * (M,mh)/(M,M) = (m,m)/(M,M), chiralities -,+,-."""
+    L, HT, DT = tiny
+    m, mh, M = 0.01, 0.1, 1.0
+    parts = [(-1, m, m, mh), (+1, m, mh, M), (-1, M, mh, M)]
+    tot = 0.0
+    for chir, m3, m4, mo in parts:
+        A, P = dense_action(O, D, L, HT, chir, m3, m4, mo)
+        tot += D.subspace_logdet(A, P)[0]
+    # the functional integral of each action is 1/det(action); the product is det D_T(m)/det D_T(M)
+    assert abs(-tot - (D.logdet(DT(m, m))[0] - D.logdet(DT(M, M))[0])) < 1e-9
+    # old MP, Eq.(old_MP): four actions -,+,-,+ give the same product
+    old = [(-1, m, m, mh), (+1, m, mh, mh), (-1, mh, mh, M), (+1, mh, M, M)]
+    tot_old = sum(D.subspace_logdet(*dense_action(O, D, L, HT, *p))[0] for p in old)
+    assert abs(tot - tot_old) < 1e-9
+
+
+def test_overlap_relation(O, D, tiny):
+    """Textbook special case: det D_odwf(m) / det D_odwf(1) = det D_ov(m), where D_ov is the
+    overlap operator with the Zolotarev-type sign function built from the same omega_s
+    (optimal DWF -> overlap).  The D_T form of Eq.(detDodwf) differs from this ratio only by
+    the link-independent factor det(1 + L(m)) / det(1 + L(1)) = [(1+m)/2]^{12V}."""
+    L, HT, DT = tiny
+    sh4 = L.shape4
+    Dw = D.dense(lambda v: L.dw(v), sh4)
+    g5 = np.kron(np.eye(L.V), np.kron(O.gamma(4), np.eye(3)))
+    n = L.V * 12
+    for m in (0.02, 0.4):
+        Dm = D.dense(lambda v: L.dodwf(v, m, m), L.shape5)
+        D1 = D.dense(lambda v: L.dodwf(v, 1.0, 1.0), L.shape5)
+        lhs = D.logdet(Dm)[0] - D.logdet(D1)[0]
+        rhs = D.overlap_logdet(Dw, g5, L.omega, m)[0]
+        assert abs(lhs - rhs) < 1e-9
+        lt = D.logdet(DT(m, m))[0] - D.logdet(DT(1.0, 1.0))[0]
+        assert abs(lt - (lhs - n * np.log((1 + m) / 2))) < 1e-9
+
+
+# ----------------------------------------------------------------- the oracle's solvers
+
+def test_ht_solve_matches_dense(O, D, tiny):
+    L, HT, DT = tiny
+    b = rand_field(L.shape5, 77)
+    for mp, mm in [(0.01, 0.01), (0.05, 1.0)]:
+        x, it, rr = L.ht_solve(b, mp, mm, tol=1e-12)
+        assert it > 0 and rr <= 1e-12
+        xd = np.linalg.solve(HT(mp, mm), b.reshape(-1)).reshape(b.shape)
+        assert np.abs(x - xd).max() < 1e-9 * np.abs(xd).max()
+
+
+def test_chiral_action_and_hinv_match_dense(O, D, tiny):
+    L, HT, DT = tiny
+    phi = IN.gaussian_spinor(L.shape4[:-2], 5)
+    for chir, m3, m4, mo in [(-1, 0.02, 0.02, 1.0), (+1, 0.02, 1.0, 1.0), (+1, 0.01, 0.1, 1.0)]:
+        out, S, info = L.chiral_action(chir, m3, m4, mo, phi, tol=1e-12)
+        A, _ = dense_action(O, D, L, HT, chir, m3, m4, mo)
+        ref = (A @ phi.reshape(-1)).reshape(phi.shape)
+        assert np.abs(out - ref).max() < 1e-9
+        assert abs(S - np.vdot(phi, ref).real) < 1e-9 * abs(S)
+        assert abs(info["S_imag"]) < 1e-10 * abs(S)
+    out, S, info = L.hinv(phi, 0.02, 1.0, tol=1e-12)
+    A1, _ = dense_action(O, D, L, HT, -1, 0.02, 0.02, 1.0)
+    A2, _ = dense_action(O, D, L, HT, +1, 0.02, 1.0, 1.0)
+    ref = ((A1 + A2) @ phi.reshape(-1)).reshape(phi.shape)
+    assert np.abs(out - ref).max() < 1e-9
+    assert S > 0
+
+
+def test_schur_complement_solves_dt(O, D):
+    """The even-odd Schur complement (textbook block elimination) reproduces the D_T solution:
+    x_o from Dhat x_o = A^{-1}(c_o - D_oe A^{-1} c_e) equals the odd part of D_T^{-1} c."""
+    dims = (2, 2, 2, 2)
+    L = lat(O, dims, eps=0.4, seed=2, Ns=4)
+    mp, mm = 0.04, 0.4
+    odd = O.parity_mask(dims)[None, ..., None, None]
+    Dd = D.dense(lambda v: L.dt(v, mp, mm), L.shape5)
+    c = rand_field(L.shape5, 31)
+    x = np.linalg.solve(Dd, c.reshape(-1)).reshape(c.shape)
+    ce = np.where(odd, 0, c)
+    t = L.at_inv(ce, mp, mm)                       # A^{-1} c_e on even sites
+    De = L.dt(t, mp, mm)                           # odd part = D_oe A^{-1} c_e
+    rhs = L.at_inv(np.where(odd, c - De, 0), mp, mm, parity=1)
+    S = D.dense(lambda v: L.schur(v, mp, mm), L.shape5)
+    mask = np.broadcast_to(odd, L.shape5).reshape(-1)
+    So = S[np.ix_(mask, mask)]
+    xo = np.linalg.solve(So, rhs.reshape(-1)[mask])
+    assert np.abs(xo - x.reshape(-1)[mask]).max() < 1e-11 * np.abs(x).max()
+    # and the adjoint
+    u, v = rand_field(L.shape5, 1) * odd, rand_field(L.shape5, 2) * odd
+    a = np.vdot(v, L.schur(u, mp, mm))
+    b = np.vdot(L.schur(v, mp, mm, dag=True), u)
+    assert abs(a - b) < 1e-12 * abs(a)
+
+
+# ----------------------------------------------------------------- inputs
+
+@pytest.mark.parametrize("Ns", [4, 8, 16])
+def test_omega_equioscillation(Ns):
+    """The R5-symmetric weights: exact R5 symmetry, positivity, range, and the Chebyshev
+    alternation of prod_j (1 - w_j x)/(1 + w_j x) on [0.05, 6.2] (n + 1 extrema of equal
+    size and alternating sign), which characterises the minimax optimum."""
+    w = IN.optimal_omega(Ns)
+    assert np.array_equal(w, w[::-1])
+    assert (w > 0).all() and w.min() >= 1 / 6.2 - 1e-12 and w.max() <= 1 / 0.05 + 1e-12
+    n = Ns // 2
+    wj = w[:n]
+    x = np.geomspace(0.05, 6.2, 400001)
+    P = np.prod([(1 - a * x) / (1 + a * x) for a in wj], axis=0)
+    a = np.abs(P)
+    idx = [0] + [i for i in range(1, len(x) - 1) if a[i] >= a[i - 1] and a[i] >= a[i + 1]] + [len(x) - 1]
+    ext = P[idx]
+    assert len(ext) == n + 1
+    assert np.ptp(np.abs(ext)) < 1e-6 * np.abs(ext).max()
+    assert np.all(np.sign(ext[1:]) == -np.sign(ext[:-1]))
+    # and the full sign-function error 1 - r(x) with r = (1 - prod T_s)/(1 + prod T_s) over all Ns weights
+    T = P * P
+    assert np.max(np.abs(1 - (1 - T) / (1 + T))) < 2 * a.max() ** 2 + 1e-15
+
+
+def test_links_su3_and_seeded():
+    U = IN.gauge_links((4, 2, 2, 2), 0.7, 3)
+    Uf = U.reshape(-1, 3, 3)
+    assert np.abs(Uf @ np.conj(np.swapaxes(Uf, 1, 2)) - np.eye(3)).max() < 1e-14
+    assert np.abs(np.linalg.det(Uf) - 1).max() < 1e-14
+    assert np.array_equal(U, IN.gauge_links((4, 2, 2, 2), 0.7, 3))
+    assert not np.array_equal(U, IN.gauge_links((4, 2, 2, 2), 0.7, 4))
+    # near-unit: tr H^2 = eps^2 sum_a theta_a^2 / 2, so <Re tr U> / 3 = 1 - 2 eps^2 / 3 + O(eps^4)
+    Us = IN.gauge_links((8, 8, 8, 8), 0.1, 5).reshape(-1, 3, 3)
+    assert abs(np.mean(np.trace(Us, axis1=1, axis2=2).real) / 3 - (1 - 2 * 0.01 / 3)) < 2e-4
+
+
+def test_gaussian_source_statistics():
+    eta = IN.gaussian_spinor((8, 8, 8, 8), 1)
+    assert abs(np.mean(np.abs(eta) ** 2) - 1.0) < 0.01
+    assert abs(np.mean(eta.real * eta.imag)) < 0.01
