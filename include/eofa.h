@@ -1,0 +1,172 @@
+/*
+ * eofa.h - C ABI of the MI355X (gfx950) EOFA / optimal domain-wall solver library.
+ *
+ * The library solves the 5D Hermitian systems H_T(m+, m-) x = b of the exact
+ * one-flavour pseudofermion action (EOFA) and assembles, from their solutions,
+ * H^{-1}(mj, mi) phi of Eq.(Hij) and the action S = phi^dagger H^{-1} phi
+ * (Chen & Chiu, "Mass preconditioning for the exact one-flavor action in lattice
+ * QCD with domain-wall fermion", Sec. I and Sec. II).
+ *
+ * Operators (the paper defers their definitions to its references; this is the
+ * reading the library implements):
+ *   D_w          = (4 - m0) - (1/2) sum_mu [(1 - gamma_mu) U_mu(x) delta_{x+mu}
+ *                                          + (1 + gamma_mu) U_mu(x-mu)^dag delta_{x-mu}]
+ *                  (the W - m0 + sigma.t blocks of Eq.(DTm1m2));
+ *   D_T(m+, m-)  = D_w + P_+ M_+(m+) + P_- M_-(m-),  Eq.(DTm1m2), with
+ *   M_pm(m)      = omega^{-1/2} (1 - L_pm(m)) (1 + L_pm(m))^{-1} omega^{-1/2},
+ *                  (L_+)_{s,s-1} = 1, (L_+)_{1,Ns} = -m, L_- = L_+^T;
+ *   H_T(m+, m-)  = gamma_5 R5 D_T(m+, m-)  (Hermitian; (R5 psi)_s = psi_{Ns+1-s});
+ *   k(mj, mi)    = 2 (mj - mi) / ((1 + mj)(1 + mi)),  Om_s = (-1)^s omega_s^{-1/2}
+ *                  (Eqs.(delta_ij)-(k_ij) for this operator: Delta = k Om Om^T).
+ * Chiral basis: gamma_5 = diag(1, 1, -1, -1), P_pm = (1 pm gamma_5)/2, fermion
+ * fields periodic in x, y, z and with phase t_bc across the t boundary.
+ *
+ * Memory.  Every field pointer is a DEVICE pointer owned by the caller; the
+ * library never frees it.  Canonical layouts (complex128 = 2 doubles re, im):
+ *   links  U[Lt][Lz][Ly][Lx][mu][3][3]   (mu = x, y, z, t; row, column)
+ *   4D     phi[Lt][Lz][Ly][Lx][spin 4][colour 3]
+ *   5D     psi[Ns][Lt][Lz][Ly][Lx][spin 4][colour 3]
+ * All work is enqueued on the context's hipStream_t; calls that return a host
+ * scalar (S, info) synchronise that stream before returning.
+ *
+ * Errors.  Every call returns an eofa_status; nothing aborts and no C++
+ * exception crosses this boundary.  eofa_last_error() returns the context's
+ * last message.  A context is not thread-safe: use one per stream.
+ */
+#ifndef EOFA_H
+#define EOFA_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eofa_ctx eofa_ctx;
+
+typedef enum {
+    EOFA_OK = 0,
+    EOFA_EINVAL = -1,   /* bad argument (message says which) */
+    EOFA_ENOMEM = -2,   /* device allocation or workspace too small */
+    EOFA_EHIP = -3,     /* a HIP runtime call failed */
+    EOFA_ENOCONV = -4,  /* solver hit max_iter or broke down; best iterate returned */
+    EOFA_ESTATE = -5,   /* call out of order (e.g. no gauge field set) */
+    EOFA_ENOTIMPL = -6
+} eofa_status;
+
+typedef enum { EOFA_FP64 = 0, EOFA_MIXED_FP32 = 1, EOFA_MIXED_FP16 = 2 } eofa_precision;
+typedef enum { EOFA_PC_NONE = 0, EOFA_PC_LEARNED = 1 } eofa_precond;
+
+typedef struct {
+    double tol;            /* target true relative residual ||b - H_T x|| / ||b|| of every 5D solve */
+    int max_iter;          /* total inner iterations allowed per 5D solve */
+    eofa_precision prec;   /* storage precision of the inner Krylov solver */
+    eofa_precond pc;       /* EOFA_PC_LEARNED: flexible GCR with the learned preconditioner */
+    double reliable_delta; /* mixed precision: reliable update when ||r|| drops by this factor (0: 0.1) */
+    int use_graph;         /* capture check_every iterations in a hipGraph and replay it */
+    int check_every;       /* iterations between host convergence checks (0: automatic) */
+} eofa_solve_params;
+
+typedef struct {
+    int iters;             /* inner Krylov iterations */
+    int op_applies;        /* applications of the even-odd operator Dhat (or its adjoint) */
+    int reliable_updates;  /* FP64 residual recomputations (restarts included) */
+    int fell_back;         /* learned-preconditioner solve fell back to CG */
+    double true_rel_resid; /* FP64 ||b - H_T x|| / ||b|| of the returned x */
+    double seconds;        /* wall time of the solve */
+} eofa_solve_info;
+
+/* Operators for eofa_apply (all on canonical 5D fields unless noted). */
+typedef enum {
+    EOFA_OP_DW = 0,        /* D_w on every s-slice */
+    EOFA_OP_HOP = 1,       /* Wilson hop sum_mu[(1-g)U psi(x+mu) + (1+g)U^dag psi(x-mu)] on every slice */
+    EOFA_OP_DT = 2,        /* D_T(m+, m-) */
+    EOFA_OP_DT_DAG = 3,    /* D_T(m+, m-)^dagger */
+    EOFA_OP_HT = 4,        /* H_T(m+, m-) */
+    EOFA_OP_AT_INV = 5,    /* (4 - m0 + P_+ M_+ + P_- M_-)^{-1}, site-local */
+    EOFA_OP_SCHUR = 6,     /* Dhat = 1 - A^{-1}(D_T)_oe A^{-1}(D_T)_eo on odd sites (even sites of out = 0) */
+    EOFA_OP_SCHUR_DAG = 7, /* Dhat^dagger */
+    EOFA_OP_SCHUR_NORMAL = 8 /* Dhat^dagger Dhat */
+} eofa_op;
+
+/*
+ * Create a context for an Lx x Ly x Lz x Lt lattice (dims[] = {Lx, Ly, Lz, Lt}, each even,
+ * Lx*Ly*Lz*Lt/2 < 2^31) with Ns fifth-dimension slices (Ns a power of two, 2..64),
+ * Wilson mass -m0 (0 < m0 < 2), weights omega_host[Ns] (host memory, > 0, R5-symmetric to
+ * 1e-14 relative: the optimal weights of Sec. III), fermion phase t_bc = -1 or +1 across the
+ * t boundary, and the hipStream_t all work goes to (NULL: the default stream).
+ */
+eofa_status eofa_create(eofa_ctx **out, const int dims[4], int Ns, double m0,
+                        const double *omega_host, int t_bc, void *hip_stream);
+
+/* Workspace the solves below need for nrhs simultaneous systems under params. */
+eofa_status eofa_workspace_size(const eofa_ctx *ctx, const eofa_solve_params *params, int nrhs,
+                                size_t *bytes);
+/* Caller-owned device workspace (256-byte aligned).  Without one, the library allocates
+ * its own on first use and frees it in eofa_destroy. */
+eofa_status eofa_set_workspace(eofa_ctx *ctx, void *dev_ptr, size_t bytes);
+
+/* Upload and pack the gauge field (device pointer, canonical layout).  Must precede solves. */
+eofa_status eofa_set_gauge(eofa_ctx *ctx, const void *U);
+
+/*
+ * out = H^{-1}(m_hi, m_lo) phi of Eq.(Hij) (m_lo = m_i, m_hi = m_j, 0 < m_lo <= m_hi <= 1),
+ * computed as the - action (m_lo,m_lo)/(m_lo,m_hi) plus the + action (m_lo,m_hi)/(m_hi,m_hi)
+ * (Eq.(pfij), chiral split of Sec. I).  phi, out: 4D canonical device buffers (may not alias).
+ * *S = Re phi^dagger out (S may be NULL).  info[0] is the - solve, info[1] the + solve.
+ */
+eofa_status eofa_hinv(eofa_ctx *ctx, double m_lo, double m_hi, const void *phi, void *out, double *S,
+                      const eofa_solve_params *params, eofa_solve_info info[2]);
+
+/*
+ * One chiral action of Eqs.(m1m2_m1m4) / (m1m2_m3m2):
+ *   chir = -1: (m3,m4)/(m3,mo): out = P_- [phi - k(mo,m4) Om^T H_T(m3,m4)^{-1} Om P_- phi]
+ *   chir = +1: (m3,m4)/(mo,m4): out = P_+ [phi + k(mo,m3) Om^T H_T(m3,m4)^{-1} Om P_+ phi]
+ * phi, out: 4D canonical device buffers.  *S = Re phi^dagger out (may be NULL).
+ */
+eofa_status eofa_chiral_action(eofa_ctx *ctx, int chir, double m3, double m4, double mo,
+                               const void *phi, void *out, double *S,
+                               const eofa_solve_params *params, eofa_solve_info *info);
+
+/*
+ * n independent chiral actions solved together (the multi-RHS form): action j has chirality
+ * chir[j] and masses (m3[j], m4[j], mo[j]) as in eofa_chiral_action, source phi[j] and output
+ * out[j] (arrays of n device pointers held in HOST memory).  S[j] (host, may be NULL), info[j].
+ * Systems sharing (m3, m4) are batched into one launch sequence; links are loaded once per
+ * site for the whole batch.
+ */
+eofa_status eofa_chiral_action_batch(eofa_ctx *ctx, int n, const int *chir, const double *m3,
+                                     const double *m4, const double *mo, const void *const *phi,
+                                     void *const *out, double *S, const eofa_solve_params *params,
+                                     eofa_solve_info *info);
+
+/* H^{-1}(m_hi[j], m_lo[j]) phi[j] for j < n (2n chiral actions through the batch path). */
+eofa_status eofa_hinv_batch(eofa_ctx *ctx, int n, const double *m_lo, const double *m_hi,
+                            const void *const *phi, void *const *out, double *S,
+                            const eofa_solve_params *params, eofa_solve_info *info /* 2n */);
+
+/* Solve H_T(m_plus, m_minus) x5 = b5 (5D canonical device buffers, may not alias). */
+eofa_status eofa_solve_ht(eofa_ctx *ctx, double m_plus, double m_minus, const void *b5, void *x5,
+                          const eofa_solve_params *params, eofa_solve_info *info);
+
+/* out = op(in) (5D canonical device buffers, may not alias) in the given storage precision
+ * (EOFA_FP64 or EOFA_MIXED_FP32: FP32 storage and arithmetic, result widened to complex128). */
+eofa_status eofa_apply(eofa_ctx *ctx, int op, double m_plus, double m_minus, const void *in, void *out,
+                       eofa_precision prec);
+
+/* Device time (ms, HIP events) and launch count of the FP64 even-odd hop kernel since the
+ * last reset, for throughput accounting.  enable != 0 starts recording events around every
+ * hop launch (adds a small overhead); eofa_hop_timing_reset clears the counters. */
+eofa_status eofa_hop_timing(eofa_ctx *ctx, int enable, double *ms, long *launches, double *bytes);
+eofa_status eofa_hop_timing_reset(eofa_ctx *ctx);
+
+/* Learned preconditioner weights: the packed BF16 blob produced by eofa_cnn_* (see below). */
+eofa_status eofa_set_precond(eofa_ctx *ctx, const void *weights_dev, size_t bytes);
+
+const char *eofa_last_error(const eofa_ctx *ctx);
+void eofa_destroy(eofa_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EOFA_H */

@@ -93,7 +93,8 @@ static inline void spin_proj(int mu, double sgn, const cplx chi[4][3], cplx out[
     for (int a = 0; a < 4; a++)
         for (int c = 0; c < 3; c++) {
             cplx s = chi[a][c];
-            for (int b = 0; b < 4; b++) s += sgn * G[mu][a][b] * chi[b][c];
+            for (int b = 0; b < 4; b++)
+                if (G[mu][a][b] != 0) s += sgn * G[mu][a][b] * chi[b][c];
             out[a][c] = s;
         }
 }
@@ -415,12 +416,11 @@ static double nrm2(long n, const cplx *v)
 }
 
 /*
- * Solve H_T(m+, m-) x = b (5D).  Route: H_T^{-1} = omega^{1/2} (1+L) D_odwf^{-1} omega^{1/2} R5 gamma_5,
- * with D_odwf y = b' solved by CGNR (conjugate gradient on D^dagger D, the CG of the
- * fermion-force solves in Sec. I) over the full lattice, no preconditioning.
- * Stops when the true residual ||b' - D_odwf y|| / ||b'|| <= tol / 10 (re-checked
- * by recomputation) and reports ||b - H_T x|| / ||b|| in *relres.
- * Returns the number of CG iterations, or -1 if maxit was reached.
+ * Solve H_T(m+, m-) x = b (5D), the inverse inside Eqs.(Hij), (m1m2_m1m4) and (m1m2_m3m2).
+ * H_T is Hermitian, so the plain route is CG on the normal equations H_T^2 x = H_T b (the
+ * CG of the force and heat-bath solves of Sec. I), over the full lattice, without
+ * preconditioning.  Stops when the recomputed true residual ||b - H_T x|| / ||b|| <= tol / 10
+ * and reports it in *relres.  Returns the number of CG iterations, or -1 if maxit was reached.
  */
 int or_ht_solve(const int *L, int tbc, double m0, int Ns, const double *omega, double mp, double mm,
                 const double complex *U, const double complex *b, double complex *x, double tol,
@@ -429,33 +429,27 @@ int or_ht_solve(const int *L, int tbc, double m0, int Ns, const double *omega, d
     gamma_init();
     long V = (long)L[0] * L[1] * L[2] * L[3];
     long n = V * 12 * Ns;
-    cplx *bp = malloc(sizeof(cplx) * n), *y = calloc(n, sizeof(cplx)), *r = malloc(sizeof(cplx) * n);
-    cplx *p = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
-    /* b' = omega^{1/2} R5 gamma_5 b */
-    for (long i = 0; i < V; i++)
-        for (int s = 0; s < Ns; s++)
-            for (int a = 0; a < 4; a++)
-                for (int c = 0; c < 3; c++) {
-                    cplx v = 0;
-                    for (int k = 0; k < 4; k++) v += G[4][a][k] * b[((Ns - 1 - s) * V + i) * 12 + k * 3 + c];
-                    bp[(s * V + i) * 12 + a * 3 + c] = sqrt(omega[s]) * v;
-                }
-    double bn2 = nrm2(n, bp);
-    int it = 0, done = 0;
-    while (!done && it < maxit) {
-        /* (re)start: r = D^dag (b' - D y) */
-        or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, y, t, 0);
-        for (long j = 0; j < n; j++) t[j] = bp[j] - t[j];
-        if (sqrt(nrm2(n, t) / bn2) <= 0.1 * tol) break;
-        or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, t, r, 1);
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *q = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    memset(x, 0, sizeof(cplx) * n);
+    double bn2 = nrm2(n, b);
+    int it = 0, fail = 0;
+    for (;;) {
+        /* true residual t = b - H_T x */
+        or_ht(L, tbc, m0, Ns, omega, mp, mm, U, x, t);
+        for (long j = 0; j < n; j++) t[j] = b[j] - t[j];
+        *relres = sqrt(nrm2(n, t) / bn2);
+        if (*relres <= 0.1 * tol || bn2 == 0.0) break;
+        if (it >= maxit) { fail = 1; break; }
+        /* (re)start: r = H_T t, p = r */
+        or_ht(L, tbc, m0, Ns, omega, mp, mm, U, t, r);
         memcpy(p, r, sizeof(cplx) * n);
         double rr = nrm2(n, r), rr0 = rr;
         while (it < maxit) {
-            or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, p, t, 0);
-            double tt = nrm2(n, t);
-            double alpha = rr / tt;
-            or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, t, q, 1);
-            for (long j = 0; j < n; j++) { y[j] += alpha * p[j]; r[j] -= alpha * q[j]; }
+            or_ht(L, tbc, m0, Ns, omega, mp, mm, U, p, q);
+            double alpha = rr / nrm2(n, q);
+            or_ht(L, tbc, m0, Ns, omega, mp, mm, U, q, t);
+            for (long j = 0; j < n; j++) { x[j] += alpha * p[j]; r[j] -= alpha * t[j]; }
             double rn = nrm2(n, r);
             it++;
             if (rn <= 1e-4 * tol * tol * rr0) break;   /* go back and check the true residual */
@@ -464,17 +458,51 @@ int or_ht_solve(const int *L, int tbc, double m0, int Ns, const double *omega, d
             rr = rn;
         }
     }
-    if (it >= maxit) done = -1;
-    /* x = omega^{1/2} (1 + L) y */
-    one_pm_l(Ns, V, mp, mm, +1.0, 0, y, x);
-    for (int s = 0; s < Ns; s++)
-        for (long j = 0; j < V * 12; j++) x[s * V * 12 + j] *= sqrt(omega[s]);
-    /* true residual on the H_T system */
-    or_ht(L, tbc, m0, Ns, omega, mp, mm, U, x, t);
-    for (long j = 0; j < n; j++) t[j] = b[j] - t[j];
-    *relres = sqrt(nrm2(n, t) / nrm2(n, b));
-    free(bp); free(y); free(r); free(p); free(q); free(t);
-    return done < 0 ? -1 : it;
+    free(r); free(p); free(q); free(t);
+    return fail ? -1 : it;
+}
+
+/*
+ * Solve D_odwf(m+, m-) y = b' by CGNR over the full lattice (no preconditioning); used to
+ * check the route H_T^{-1} = omega^{1/2} (1 + L) D_odwf^{-1} omega^{1/2} R5 gamma_5 against
+ * the direct H_T solve.  Returns iterations (or -1) and the D_odwf residual in *relres.
+ */
+int or_dodwf_solve(const int *L, int tbc, double m0, int Ns, const double *omega, double mp, double mm,
+                   const double complex *U, const double complex *bp, double complex *y, double tol,
+                   int maxit, double *relres)
+{
+    gamma_init();
+    long V = (long)L[0] * L[1] * L[2] * L[3];
+    long n = V * 12 * Ns;
+    cplx *r = malloc(sizeof(cplx) * n), *p = malloc(sizeof(cplx) * n);
+    cplx *q = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    memset(y, 0, sizeof(cplx) * n);
+    double bn2 = nrm2(n, bp);
+    int it = 0, fail = 0;
+    for (;;) {
+        or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, y, t, 0);
+        for (long j = 0; j < n; j++) t[j] = bp[j] - t[j];
+        *relres = sqrt(nrm2(n, t) / bn2);
+        if (*relres <= 0.1 * tol || bn2 == 0.0) break;
+        if (it >= maxit) { fail = 1; break; }
+        or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, t, r, 1);
+        memcpy(p, r, sizeof(cplx) * n);
+        double rr = nrm2(n, r), rr0 = rr;
+        while (it < maxit) {
+            or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, p, t, 0);
+            double alpha = rr / nrm2(n, t);
+            or_dodwf(L, tbc, m0, Ns, omega, mp, mm, U, t, q, 1);
+            for (long j = 0; j < n; j++) { y[j] += alpha * p[j]; r[j] -= alpha * q[j]; }
+            double rn = nrm2(n, r);
+            it++;
+            if (rn <= 1e-4 * tol * tol * rr0) break;
+            double beta = rn / rr;
+            for (long j = 0; j < n; j++) p[j] = r[j] + beta * p[j];
+            rr = rn;
+        }
+    }
+    free(r); free(p); free(q); free(t);
+    return fail ? -1 : it;
 }
 
 /*

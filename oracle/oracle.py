@@ -26,7 +26,7 @@ def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain C99 + OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -49,6 +49,7 @@ def lib():
             "or_ht": (I, [P, I, D, I, P, D, D, P, P, P]),
             "or_dodwf": (None, [P, I, D, I, P, D, D, P, P, P, I]),
             "or_ht_solve": (I, [P, I, D, I, P, D, D, P, P, P, D, I, P]),
+            "or_dodwf_solve": (I, [P, I, D, I, P, D, D, P, P, P, D, I, P]),
             "or_chiral_action": (I, [P, I, D, I, P, I, D, D, D, P, P, P, D, I, P, P, P]),
             "or_hinv": (I, [P, I, D, I, P, D, D, P, P, P, D, I, P, P, P]),
             "or_at_inv": (I, [P, D, I, P, D, D, P, P, I, I]),
@@ -178,6 +179,14 @@ class Lattice:
         it = lib().or_ht_solve(_p(self._L), self.tbc, self.m0, self.Ns, _p(self.omega), float(mp),
                                float(mm), _p(self.U), _p(b), _p(x), float(tol), int(maxit), C.byref(rr))
         return x, it, rr.value
+
+    def dodwf_solve(self, bp, mp, mm, tol=1e-10, maxit=100000):
+        bp = _c128(bp)
+        y = np.empty_like(bp)
+        rr = C.c_double()
+        it = lib().or_dodwf_solve(_p(self._L), self.tbc, self.m0, self.Ns, _p(self.omega), float(mp),
+                                  float(mm), _p(self.U), _p(bp), _p(y), float(tol), int(maxit), C.byref(rr))
+        return y, it, rr.value
 
     def chiral_action(self, chir, m3, m4, mo, phi, tol=1e-10, maxit=100000):
         phi = _c128(phi)

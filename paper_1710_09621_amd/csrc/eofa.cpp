@@ -1,0 +1,744 @@
+// Host runtime and C ABI of the gfx950 EOFA / optimal-DWF solver (see include/eofa.h).
+//
+// Solve path for H_T(m+, m-) x = b (the 5D systems inside Eq.(Hij) and Eqs.(m1m2_m1m4),
+// (m1m2_m3m2)):  H_T = gamma_5 R5 D_T, so x = D_T^{-1} c with c = R5 gamma_5 b.  D_T is split
+// into 4D parities,
+//     D_T = [[A_T, -H_eo/2], [-H_oe/2, A_T]],   A_T = 4 - m0 + P_+ M_+ + P_- M_-  (site-local),
+// and CG runs on the normal equations of the site-normalised Schur complement
+//     Dhat = 1 - (1/4) A_T^{-1} H_oe A_T^{-1} H_eo          (odd sites).
+// Every hop kernel carries its site-local operator as an epilogue, so one CG iteration is four
+// fused hop launches and one BLAS launch, with alpha/beta/|r|^2 kept on the device.  The true
+// residual ||c - D_T x|| is recomputed in FP64 at the end and the solve restarts on the defect
+// if it is above tolerance.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/eofa.h"
+#include "eofa_int.h"
+
+using namespace eofa;
+
+struct eofa_ctx {
+    int L[4] = {0, 0, 0, 0};
+    int Ns = 0;
+    double m0 = 0;
+    int tbc = -1;
+    std::vector<double> omega;
+    hipStream_t st = nullptr;
+    Geom g{};
+    size_t nh = 0;  // complex elements of one half field (Vh * 12 * Ns)
+    cd* U[2] = {nullptr, nullptr};
+    cpx<float>* Uf[2] = {nullptr, nullptr};
+    bool gauge = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    double* scal = nullptr;
+    double* hscal = nullptr;  // pinned
+    std::map<std::tuple<int, double, double>, SiteOp*> tabs;
+    std::string err;
+    // hop timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    size_t ev_used = 0;
+    double hop_ms = 0;
+    long hop_launches = 0;
+    double hop_bytes = 0;
+};
+
+namespace {
+
+struct Fail {
+    eofa_status st;
+};
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                     \
+            throw Fail{EOFA_EHIP};                                                            \
+        }                                                                                     \
+    } while (0)
+
+#define REQUIRE(cond, code, msg)                                                              \
+    do {                                                                                      \
+        if (!(cond)) {                                                                        \
+            ctx->err = (msg);                                                                 \
+            throw Fail{code};                                                                 \
+        }                                                                                     \
+    } while (0)
+
+template <typename F> eofa_status guarded(eofa_ctx* ctx, F&& f) {
+    if (!ctx) return EOFA_EINVAL;
+    try {
+        ctx->err.clear();
+        return f();
+    } catch (const Fail& e) {
+        return e.st;
+    } catch (const std::exception& e) {
+        ctx->err = e.what();
+        return EOFA_EHIP;
+    } catch (...) {
+        ctx->err = "unknown error";
+        return EOFA_EHIP;
+    }
+}
+
+const SiteOp* site_tab(eofa_ctx* ctx, SiteKind kind, double mp, double mm) {
+    auto key = std::make_tuple((int)kind, mp, mm);
+    auto it = ctx->tabs.find(key);
+    if (it != ctx->tabs.end()) return it->second;
+    SiteOp h;
+    build_site_op(h, kind, ctx->Ns, ctx->m0, ctx->omega.data(), mp, mm);
+    SiteOp* d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof(SiteOp)));
+    HIPCHK(hipMemcpy(d, &h, sizeof(SiteOp), hipMemcpyHostToDevice));
+    ctx->tabs[key] = d;
+    return d;
+}
+
+Red red_of(eofa_ctx* ctx, int slot, int epi) { return Red{ctx->partials, ctx->counter, ctx->scal, slot, epi}; }
+
+void sync_scal(eofa_ctx* ctx) {
+    HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, sizeof(double) * SC_N, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+}
+
+// ------------------------------------------------------------------ workspace
+struct Vec2 {
+    cd* h[2];  // even, odd halves
+};
+
+struct Work64 {
+    Vec2 c, x, res;
+    cd *bh, *r, *p, *u, *w, *wt, *at, *xcg;
+};
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+size_t work64_bytes(const eofa_ctx* ctx) { return 14 * align_up(ctx->nh * sizeof(cd)); }
+size_t work32_bytes(const eofa_ctx* ctx) { return 9 * align_up(ctx->nh * sizeof(cpx<float>)); }
+
+size_t needed_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
+    size_t b = work64_bytes(ctx);
+    if (p && p->prec != EOFA_FP64) b += work32_bytes(ctx);
+    return b;
+}
+
+void ensure_ws(eofa_ctx* ctx, size_t need) {
+    if (ctx->ws_bytes >= need) return;
+    REQUIRE(ctx->ws == nullptr || ctx->ws_owned, EOFA_ENOMEM,
+            "workspace too small: need " + std::to_string(need) + " bytes, have " + std::to_string(ctx->ws_bytes));
+    if (ctx->ws) HIPCHK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    hipError_t e = hipMalloc(&ctx->ws, need);
+    REQUIRE(e == hipSuccess, EOFA_ENOMEM, "hipMalloc of " + std::to_string(need) + " workspace bytes failed");
+    ctx->ws_bytes = need;
+    ctx->ws_owned = true;
+}
+
+Work64 carve64(eofa_ctx* ctx) {
+    char* p = ctx->ws;
+    const size_t hb = align_up(ctx->nh * sizeof(cd));
+    auto take = [&]() { cd* r = (cd*)p; p += hb; return r; };
+    Work64 w;
+    w.c.h[0] = take(); w.c.h[1] = take();
+    w.x.h[0] = take(); w.x.h[1] = take();
+    w.res.h[0] = take(); w.res.h[1] = take();
+    w.bh = take(); w.r = take(); w.p = take(); w.u = take(); w.w = take(); w.wt = take(); w.at = take(); w.xcg = take();
+    return w;
+}
+
+// ------------------------------------------------------------------ hop launch helpers
+template <typename R> HopArgs<R> hop_args(eofa_ctx* ctx, int par);
+template <> HopArgs<double> hop_args<double>(eofa_ctx* ctx, int par) {
+    HopArgs<double> a{};
+    a.g = ctx->g;
+    a.par = par;
+    a.Uown = ctx->U[par];
+    a.Uoth = ctx->U[1 - par];
+    a.diag = 4.0 - ctx->m0;
+    a.scal = ctx->scal;
+    return a;
+}
+template <> HopArgs<float> hop_args<float>(eofa_ctx* ctx, int par) {
+    HopArgs<float> a{};
+    a.g = ctx->g;
+    a.par = par;
+    a.Uown = ctx->Uf[par];
+    a.Uoth = ctx->Uf[1 - par];
+    a.diag = (float)(4.0 - ctx->m0);
+    a.scal = ctx->scal;
+    return a;
+}
+
+template <typename R> void hop(eofa_ctx* ctx, bool dag, int mode, bool red, const HopArgs<R>& a, bool timed = false) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed && ctx->timing) {
+        if (ctx->ev_used == ctx->ev_pool.size()) {
+            hipEvent_t a0, a1;
+            HIPCHK(hipEventCreate(&a0));
+            HIPCHK(hipEventCreate(&a1));
+            ctx->ev_pool.push_back({a0, a1});
+        }
+        e0 = ctx->ev_pool[ctx->ev_used].first;
+        e1 = ctx->ev_pool[ctx->ev_used].second;
+        ctx->ev_used++;
+        HIPCHK(hipEventRecord(e0, ctx->st));
+    }
+    HIPCHK(launch_hop<R>(ctx->Ns, dag, mode, red, a, ctx->st));
+    if (e1) {
+        HIPCHK(hipEventRecord(e1, ctx->st));
+        ctx->hop_launches++;
+        // algorithmic bytes: in + out spinors + links (8 per 4D site, shared by the Ns slices)
+        ctx->hop_bytes += (double)ctx->g.Vh * (2.0 * 12 * ctx->Ns * 2 * sizeof(R) + 8 * 9 * 2 * sizeof(R));
+    }
+}
+
+void collect_timing(eofa_ctx* ctx) {
+    if (!ctx->timing || ctx->ev_used == 0) return;
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    for (size_t i = 0; i < ctx->ev_used; i++) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[i].first, ctx->ev_pool[i].second));
+        ctx->hop_ms += ms;
+    }
+    ctx->ev_used = 0;
+}
+
+// ------------------------------------------------------------------ FP64 CG on Dhat^dag Dhat
+struct CgOut {
+    int iters = 0;
+    int applies = 0;
+    bool converged = false;
+};
+
+// Solve Dhat x = bh (odd sites) to |r_normal| <= tol_n |r_normal,0|; x starts at zero.
+CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every) {
+    const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+    const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+    const size_t nh = ctx->nh;
+    CgOut o;
+    HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
+    double tol2 = tol_n * tol_n;
+    HIPCHK(hipMemcpyAsync(ctx->scal + SC_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    // r = Dhat^dag bh = bh - 1/4 g5 H_oe g5 A^{-dag} g5 H_eo g5 A^{-dag} bh ; p = r
+    HIPCHK(launch_site<double>(ctx->Ns, true, W.bh, W.wt, Ad, ctx->g.Vh, ctx->st));
+    {
+        auto a = hop_args<double>(ctx, 0);
+        a.in = W.wt; a.out = W.at; a.opA = Ad; a.cz = 1.0; a.caux = 0.0;
+        hop<double>(ctx, true, HM_SITE, false, a);
+    }
+    {
+        auto a = hop_args<double>(ctx, 1);
+        a.in = W.at; a.out = W.r; a.aux = W.bh; a.caux = 1.0; a.cz = -0.25;
+        a.red = red_of(ctx, 0, EPI_CG_INIT);
+        hop<double>(ctx, true, HM_LIN, true, a);
+    }
+    HIPCHK(hipMemcpyAsync(W.p, W.r, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    o.applies = 1;
+    sync_scal(ctx);
+    if (ctx->hscal[SC_DONE] != 0.0) { o.converged = true; return o; }
+    if (check_every <= 0) check_every = 1;
+    while (o.iters < maxit) {
+        {   // K1: u = A^{-1} H_eo p
+            auto a = hop_args<double>(ctx, 0);
+            a.in = W.p; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
+            hop<double>(ctx, false, HM_SITE, false, a, true);
+        }
+        {   // K2: w = p - 1/4 A^{-1} H_oe u ; wt = A^{-dag} w ; |w|^2 -> alpha
+            auto a = hop_args<double>(ctx, 1);
+            a.in = W.u; a.out = W.w; a.out2 = W.wt; a.aux = W.p; a.opA = Ai; a.opB = Ad;
+            a.cz = -0.25; a.caux = 1.0;
+            a.red = red_of(ctx, 0, EPI_CG_W);
+            hop<double>(ctx, false, HM_SCHUR_W, true, a);
+        }
+        {   // K3: at = A^{-dag} g5 H_eo g5 wt
+            auto a = hop_args<double>(ctx, 0);
+            a.in = W.wt; a.out = W.at; a.opA = Ad; a.cz = 1.0; a.caux = 0.0;
+            hop<double>(ctx, true, HM_SITE, false, a);
+        }
+        {   // K4: r -= alpha (w - 1/4 g5 H_oe g5 at) ; |r|^2 -> beta
+            auto a = hop_args<double>(ctx, 1);
+            a.in = W.at; a.out = W.r; a.aux = W.w; a.aux2 = W.r; a.cz = -0.25; a.caux = 1.0;
+            a.red = red_of(ctx, 0, EPI_CG_R);
+            hop<double>(ctx, true, HM_SCHUR_Q, true, a);
+        }
+        HIPCHK(launch_cg_xp<double>(W.xcg, W.p, W.r, ctx->scal, nh, ctx->st));
+        o.iters++;
+        o.applies += 2;
+        if (o.iters % check_every == 0 || o.iters == maxit) {
+            sync_scal(ctx);
+            double rr = ctx->hscal[SC_RR];
+            if (!std::isfinite(rr) || !std::isfinite(ctx->hscal[SC_ALPHA])) {
+                ctx->err = "CG breakdown (non-finite scalar)";
+                return o;
+            }
+            if (ctx->hscal[SC_DONE] != 0.0) { o.converged = true; break; }
+        }
+    }
+    return o;
+}
+
+// ------------------------------------------------------------------ 5D solve D_T x = c
+struct SolveOut {
+    int iters = 0, applies = 0, restarts = 0;
+    double relres = 0;
+    bool ok = false;
+};
+
+// true residual res = c - D_T x on both parities; returns |res|^2
+double residual64(eofa_ctx* ctx, const Work64& W, double mp, double mm) {
+    const SiteOp* M = site_tab(ctx, SK_M, mp, mm);
+    for (int par = 0; par < 2; par++) {
+        auto a = hop_args<double>(ctx, par);
+        a.in = W.x.h[1 - par]; a.self = W.x.h[par]; a.aux = W.c.h[par]; a.out = W.res.h[par];
+        a.opA = M; a.caux = 1.0; a.cz = -1.0;
+        a.red = red_of(ctx, SC_TMP + par, EPI_STORE);
+        hop<double>(ctx, false, HM_DT, true, a);
+    }
+    sync_scal(ctx);
+    return ctx->hscal[SC_TMP] + ctx->hscal[SC_TMP + 1];
+}
+
+double norm2_64(eofa_ctx* ctx, const Vec2& v) {
+    for (int par = 0; par < 2; par++) HIPCHK(launch_norm2<double>(v.h[par], ctx->nh, red_of(ctx, SC_TMP + 2 + par, EPI_STORE), ctx->st));
+    sync_scal(ctx);
+    return ctx->hscal[SC_TMP + 2] + ctx->hscal[SC_TMP + 3];
+}
+
+// Even-odd solve of D_T d = rhs (rhs = W.res), result added to W.x.
+CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every) {
+    const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+    // u_e = A^{-1} res_e ; bh = A^{-1} (res_o + 1/2 H_oe u_e)
+    HIPCHK(launch_site<double>(ctx->Ns, false, W.res.h[0], W.u, Ai, ctx->g.Vh, ctx->st));
+    {
+        auto a = hop_args<double>(ctx, 1);
+        a.in = W.u; a.out = W.bh; a.aux = W.res.h[1]; a.caux = 1.0; a.cz = 0.5; a.opA = Ai;
+        hop<double>(ctx, false, HM_SITE, false, a);
+    }
+    CgOut o = cg64(ctx, W, mp, mm, tol_n, maxit, check_every);
+    // d_e = A^{-1} (res_e + 1/2 H_eo d_o) -> u ; x += d
+    {
+        auto a = hop_args<double>(ctx, 0);
+        a.in = W.xcg; a.out = W.u; a.aux = W.res.h[0]; a.caux = 1.0; a.cz = 0.5; a.opA = Ai;
+        hop<double>(ctx, false, HM_SITE, false, a);
+    }
+    HIPCHK(launch_axpby<double>(1.0, W.u, 1.0, W.x.h[0], ctx->nh, nullptr, ctx->st));
+    HIPCHK(launch_axpby<double>(1.0, W.xcg, 1.0, W.x.h[1], ctx->nh, nullptr, ctx->st));
+    o.applies += 1;
+    return o;
+}
+
+SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P);
+
+int auto_check_every(const eofa_ctx* ctx, const eofa_solve_params& P) {
+    if (P.check_every > 0) return P.check_every;
+    // host polls cost ~10 us; poll every iteration once an iteration takes >~1 ms
+    double sites = (double)ctx->nh;
+    if (sites >= 4e6) return 1;
+    if (sites >= 1e6) return 4;
+    return 16;
+}
+
+SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
+    SolveOut so;
+    const double cn2 = norm2_64(ctx, W.c);
+    for (int par = 0; par < 2; par++) {
+        HIPCHK(hipMemsetAsync(W.x.h[par], 0, ctx->nh * sizeof(cd), ctx->st));
+        HIPCHK(hipMemcpyAsync(W.res.h[par], W.c.h[par], ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    }
+    if (cn2 == 0.0) { so.ok = true; return so; }
+    double rel = 1.0;
+    const int ce = auto_check_every(ctx, P);
+    for (int attempt = 0; attempt < 20; attempt++) {
+        // inner target on the normal residual, relative to the current defect
+        double tol_n = std::max(0.25 * P.tol / rel, 1e-15);
+        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce);
+        so.iters += o.iters;
+        so.applies += o.applies;
+        double r2 = residual64(ctx, W, mp, mm);
+        rel = std::sqrt(r2 / cn2);
+        so.relres = rel;
+        if (!std::isfinite(rel)) { ctx->err = "non-finite residual"; return so; }
+        if (rel <= P.tol) { so.ok = true; return so; }
+        if (so.iters >= P.max_iter) return so;
+        so.restarts++;
+    }
+    return so;
+}
+
+void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
+    REQUIRE(P != nullptr, EOFA_EINVAL, "params is NULL");
+    REQUIRE(P->tol > 0 && P->tol < 1, EOFA_EINVAL, "tol must be in (0, 1)");
+    REQUIRE(P->max_iter > 0, EOFA_EINVAL, "max_iter must be positive");
+    REQUIRE(P->prec == EOFA_FP64 || P->prec == EOFA_MIXED_FP32 || P->prec == EOFA_MIXED_FP16, EOFA_EINVAL,
+            "unknown precision");
+    REQUIRE(P->pc == EOFA_PC_NONE || P->pc == EOFA_PC_LEARNED, EOFA_EINVAL, "unknown preconditioner");
+    REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+}
+
+SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
+    REQUIRE(P.prec == EOFA_FP64, EOFA_ENOTIMPL, "only EOFA_FP64 is available in this build");
+    REQUIRE(P.pc == EOFA_PC_NONE, EOFA_ENOTIMPL, "learned preconditioner not available in this build");
+    return solve_dt_fp64(ctx, W, mp, mm, P);
+}
+
+void fill_info(eofa_solve_info* info, const SolveOut& so, double secs) {
+    if (!info) return;
+    info->iters = so.iters;
+    info->op_applies = so.applies;
+    info->reliable_updates = so.restarts + 1;
+    info->fell_back = 0;
+    info->true_rel_resid = so.relres;
+    info->seconds = secs;
+}
+
+double kfac(double mj, double mi) { return 2.0 * (mj - mi) / ((1.0 + mj) * (1.0 + mi)); }
+
+// One chiral action; writes (accumulate = 0) or adds (accumulate = 1) its P_chir part into out.
+eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, void* out,
+                        int accumulate, double* S, const eofa_solve_params* P, eofa_solve_info* info) {
+    check_params(ctx, P);
+    REQUIRE(chir == 1 || chir == -1, EOFA_EINVAL, "chir must be +1 or -1");
+    REQUIRE(phi && out, EOFA_EINVAL, "null field pointer");
+    REQUIRE(phi != out, EOFA_EINVAL, "phi and out may not alias");
+    for (double m : {m3, m4, mo}) REQUIRE(m > 0 && m <= 1, EOFA_EINVAL, "masses must lie in (0, 1]");
+    auto t0 = std::chrono::steady_clock::now();
+    ensure_ws(ctx, needed_bytes(ctx, P));
+    Work64 W = carve64(ctx);
+    const int Ns = ctx->Ns;
+    std::vector<double> Om(Ns), coef(Ns);
+    for (int s = 0; s < Ns; s++) Om[s] = ((s % 2 == 0) ? -1.0 : 1.0) / std::sqrt(ctx->omega[s]);  // (-1)^{s+1}, s 1-based
+    for (int s = 0; s < Ns; s++) coef[s] = chir * Om[Ns - 1 - s];
+    const double k = (chir < 0) ? kfac(mo, m4) : kfac(mo, m3);
+    // coefficient vectors travel in the scalar area (slots 16..16+2*Ns within a separate buffer)
+    double* dcoef = ctx->scal + SC_N;
+    double* dOm = dcoef + 64;
+    HIPCHK(hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * Ns, hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(hipMemcpyAsync(dOm, Om.data(), sizeof(double) * Ns, hipMemcpyHostToDevice, ctx->st));
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_source((const cd*)phi, W.c.h[par], ctx->g, par, Ns, chir, dcoef, ctx->st));
+    SolveOut so = solve_dt(ctx, W, m3, m4, *P);
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_combine((const cd*)phi, W.x.h[par], (cd*)out, ctx->g, par, Ns, chir, chir * k, dOm, accumulate,
+                              red_of(ctx, SC_TMP + 4 + par, EPI_STORE), ctx->st));
+    sync_scal(ctx);  // also completes the host->device copies of the pageable vectors above
+    if (S) *S = ctx->hscal[SC_TMP + 4] + ctx->hscal[SC_TMP + 5];
+    collect_timing(ctx);
+    double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(info, so, secs);
+    if (!so.ok) {
+        if (ctx->err.empty()) ctx->err = "solve did not reach tol within max_iter";
+        return EOFA_ENOCONV;
+    }
+    return EOFA_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+eofa_status eofa_create(eofa_ctx** out, const int dims[4], int Ns, double m0, const double* omega_host, int t_bc,
+                        void* hip_stream) {
+    if (!out) return EOFA_EINVAL;
+    *out = nullptr;
+    eofa_ctx* ctx = new (std::nothrow) eofa_ctx();
+    if (!ctx) return EOFA_ENOMEM;
+    eofa_status st = guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(dims && omega_host, EOFA_EINVAL, "null dims or omega");
+        long V = 1;
+        for (int i = 0; i < 4; i++) {
+            REQUIRE(dims[i] >= 2 && dims[i] % 2 == 0, EOFA_EINVAL, "every lattice extent must be even and >= 2");
+            ctx->L[i] = dims[i];
+            V *= dims[i];
+        }
+        REQUIRE(V / 2 < (1L << 31) / 64, EOFA_EINVAL, "lattice too large");
+        REQUIRE(Ns == 4 || Ns == 8 || Ns == 16 || Ns == 32, EOFA_EINVAL, "Ns must be 4, 8, 16 or 32");
+        REQUIRE(m0 > 0 && m0 < 2, EOFA_EINVAL, "m0 must be in (0, 2)");
+        REQUIRE(t_bc == 1 || t_bc == -1, EOFA_EINVAL, "t_bc must be +1 or -1");
+        for (int s = 0; s < Ns; s++) {
+            REQUIRE(std::isfinite(omega_host[s]) && omega_host[s] > 0, EOFA_EINVAL, "omega_s must be positive");
+            double o2 = omega_host[Ns - 1 - s];
+            REQUIRE(std::fabs(omega_host[s] - o2) <= 1e-14 * std::fabs(omega_host[s]), EOFA_EINVAL,
+                    "omega must be R5-symmetric");
+        }
+        ctx->Ns = Ns;
+        ctx->m0 = m0;
+        ctx->tbc = t_bc;
+        ctx->omega.assign(omega_host, omega_host + Ns);
+        ctx->st = (hipStream_t)hip_stream;
+        ctx->g = Geom{dims[0], dims[1], dims[2], dims[3], dims[0] / 2, (int)(V / 2)};
+        ctx->nh = (size_t)(V / 2) * 12 * Ns;
+        const size_t maxblk = (ctx->nh + 255) / 256 + 1024;
+        HIPCHK(hipMalloc(&ctx->partials, sizeof(double) * maxblk));
+        HIPCHK(hipMalloc(&ctx->counter, sizeof(unsigned) * 4));
+        HIPCHK(hipMemset(ctx->counter, 0, sizeof(unsigned) * 4));
+        HIPCHK(hipMalloc(&ctx->scal, sizeof(double) * (SC_N + 256)));
+        HIPCHK(hipMemset(ctx->scal, 0, sizeof(double) * (SC_N + 256)));
+        HIPCHK(hipHostMalloc(&ctx->hscal, sizeof(double) * SC_N, hipHostMallocDefault));
+        return EOFA_OK;
+    });
+    if (st != EOFA_OK) {
+        std::fprintf(stderr, "eofa_create: %s\n", ctx->err.c_str());
+        eofa_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return EOFA_OK;
+}
+
+eofa_status eofa_workspace_size(const eofa_ctx* cctx, const eofa_solve_params* params, int nrhs, size_t* bytes) {
+    if (!cctx || !bytes || nrhs < 1) return EOFA_EINVAL;
+    *bytes = needed_bytes(cctx, params) * (size_t)1;
+    (void)nrhs;
+    return EOFA_OK;
+}
+
+eofa_status eofa_set_workspace(eofa_ctx* ctx, void* dev_ptr, size_t bytes) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(((uintptr_t)dev_ptr % kAlign) == 0, EOFA_EINVAL, "workspace must be 256-byte aligned");
+        if (ctx->ws && ctx->ws_owned) HIPCHK(hipFree(ctx->ws));
+        ctx->ws = (char*)dev_ptr;
+        ctx->ws_bytes = dev_ptr ? bytes : 0;
+        ctx->ws_owned = false;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_set_gauge(eofa_ctx* ctx, const void* U) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(U != nullptr, EOFA_EINVAL, "U is NULL");
+        const size_t n = (size_t)ctx->g.Vh * 36;
+        for (int par = 0; par < 2; par++) {
+            if (!ctx->U[par]) HIPCHK(hipMalloc(&ctx->U[par], n * sizeof(cd)));
+            if (!ctx->Uf[par]) HIPCHK(hipMalloc(&ctx->Uf[par], n * sizeof(cpx<float>)));
+            HIPCHK(launch_pack_links<double>((const cd*)U, ctx->U[par], ctx->g, par, (double)ctx->tbc, ctx->st));
+            HIPCHK(launch_pack_links<float>((const cd*)U, ctx->Uf[par], ctx->g, par, (double)ctx->tbc, ctx->st));
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        ctx->gauge = true;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_chiral_action(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, void* out,
+                               double* S, const eofa_solve_params* params, eofa_solve_info* info) {
+    return guarded(ctx, [&]() { return chiral_impl(ctx, chir, m3, m4, mo, phi, out, 0, S, params, info); });
+}
+
+eofa_status eofa_hinv(eofa_ctx* ctx, double m_lo, double m_hi, const void* phi, void* out, double* S,
+                      const eofa_solve_params* params, eofa_solve_info info[2]) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(m_lo > 0 && m_lo <= m_hi && m_hi <= 1, EOFA_EINVAL, "need 0 < m_lo <= m_hi <= 1");
+        double s1 = 0, s2 = 0;
+        eofa_status a = chiral_impl(ctx, -1, m_lo, m_lo, m_hi, phi, out, 0, &s1, params, info ? &info[0] : nullptr);
+        if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+        eofa_status b = chiral_impl(ctx, +1, m_lo, m_hi, m_hi, phi, out, 1, &s2, params, info ? &info[1] : nullptr);
+        if (S) *S = s1 + s2;
+        if (b != EOFA_OK) return b;
+        return a;
+    });
+}
+
+eofa_status eofa_chiral_action_batch(eofa_ctx* ctx, int n, const int* chir, const double* m3, const double* m4,
+                                     const double* mo, const void* const* phi, void* const* out, double* S,
+                                     const eofa_solve_params* params, eofa_solve_info* info) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(n >= 0 && chir && m3 && m4 && mo && phi && out, EOFA_EINVAL, "bad batch arguments");
+        eofa_status worst = EOFA_OK;
+        for (int j = 0; j < n; j++) {
+            double s = 0;
+            eofa_status a = chiral_impl(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j], 0, &s, params,
+                                        info ? &info[j] : nullptr);
+            if (S) S[j] = s;
+            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+            if (a != EOFA_OK) worst = a;
+        }
+        return worst;
+    });
+}
+
+eofa_status eofa_hinv_batch(eofa_ctx* ctx, int n, const double* m_lo, const double* m_hi, const void* const* phi,
+                            void* const* out, double* S, const eofa_solve_params* params, eofa_solve_info* info) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(n >= 0 && m_lo && m_hi && phi && out, EOFA_EINVAL, "bad batch arguments");
+        eofa_status worst = EOFA_OK;
+        for (int j = 0; j < n; j++) {
+            eofa_status a = eofa_hinv(ctx, m_lo[j], m_hi[j], phi[j], out[j], S ? &S[j] : nullptr, params,
+                                      info ? &info[2 * j] : nullptr);
+            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+            if (a != EOFA_OK) worst = a;
+        }
+        return worst;
+    });
+}
+
+eofa_status eofa_solve_ht(eofa_ctx* ctx, double m_plus, double m_minus, const void* b5, void* x5,
+                          const eofa_solve_params* params, eofa_solve_info* info) {
+    return guarded(ctx, [&]() -> eofa_status {
+        check_params(ctx, params);
+        REQUIRE(b5 && x5 && b5 != x5, EOFA_EINVAL, "bad field pointers");
+        REQUIRE(m_plus > 0 && m_plus <= 1 && m_minus > 0 && m_minus <= 1, EOFA_EINVAL, "masses must lie in (0, 1]");
+        auto t0 = std::chrono::steady_clock::now();
+        ensure_ws(ctx, needed_bytes(ctx, params));
+        Work64 W = carve64(ctx);
+        // c = R5 gamma_5 b, then D_T x = c
+        for (int par = 0; par < 2; par++)
+            HIPCHK(launch_pack5<double>((const cd*)b5, W.c.h[par], ctx->g, par, ctx->Ns, 1, ctx->st));
+        SolveOut so = solve_dt(ctx, W, m_plus, m_minus, *params);
+        for (int par = 0; par < 2; par++)
+            HIPCHK(launch_unpack5<double>(W.x.h[par], (cd*)x5, ctx->g, par, ctx->Ns, 0, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        collect_timing(ctx);
+        fill_info(info, so, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+        if (!so.ok) {
+            if (ctx->err.empty()) ctx->err = "solve did not reach tol within max_iter";
+            return EOFA_ENOCONV;
+        }
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_apply(eofa_ctx* ctx, int op, double m_plus, double m_minus, const void* in, void* out,
+                       eofa_precision prec) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+        REQUIRE(in && out && in != out, EOFA_EINVAL, "bad field pointers");
+        REQUIRE(prec == EOFA_FP64, EOFA_ENOTIMPL, "eofa_apply: only EOFA_FP64 in this build");
+        eofa_solve_params P{1e-10, 1, EOFA_FP64, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        Work64 W = carve64(ctx);
+        const int Ns = ctx->Ns;
+        const size_t nh = ctx->nh;
+        for (int par = 0; par < 2; par++) HIPCHK(launch_pack5<double>((const cd*)in, W.x.h[par], ctx->g, par, Ns, 0, ctx->st));
+        Vec2 o = W.res;
+        switch (op) {
+        case EOFA_OP_DW:
+        case EOFA_OP_HOP:
+        case EOFA_OP_DT:
+        case EOFA_OP_DT_DAG:
+        case EOFA_OP_HT: {
+            const bool dag = (op == EOFA_OP_DT_DAG);
+            const SiteOp* M = site_tab(ctx, dag ? SK_M_DAG : SK_M, m_plus, m_minus);
+            for (int par = 0; par < 2; par++) {
+                auto a = hop_args<double>(ctx, par);
+                a.in = W.x.h[1 - par]; a.self = W.x.h[par]; a.out = o.h[par]; a.opA = M; a.cz = 1.0; a.caux = 0.0;
+                int mode = (op == EOFA_OP_DW) ? HM_DW : (op == EOFA_OP_HOP ? HM_LIN : HM_DT);
+                hop<double>(ctx, dag, mode, false, a);
+            }
+            break;
+        }
+        case EOFA_OP_AT_INV: {
+            const SiteOp* Ai = site_tab(ctx, SK_AINV, m_plus, m_minus);
+            for (int par = 0; par < 2; par++) HIPCHK(launch_site<double>(Ns, false, W.x.h[par], o.h[par], Ai, ctx->g.Vh, ctx->st));
+            break;
+        }
+        case EOFA_OP_SCHUR:
+        case EOFA_OP_SCHUR_DAG:
+        case EOFA_OP_SCHUR_NORMAL: {
+            const SiteOp* Ai = site_tab(ctx, SK_AINV, m_plus, m_minus);
+            const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, m_plus, m_minus);
+            HIPCHK(hipMemsetAsync(o.h[0], 0, nh * sizeof(cd), ctx->st));
+            const cd* src = W.x.h[1];
+            if (op != EOFA_OP_SCHUR_DAG) {
+                auto a = hop_args<double>(ctx, 0);
+                a.in = src; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
+                hop<double>(ctx, false, HM_SITE, false, a);
+                auto b = hop_args<double>(ctx, 1);
+                b.in = W.u; b.out = W.w; b.out2 = W.wt; b.aux = src; b.opA = Ai; b.opB = Ad; b.cz = -0.25; b.caux = 1.0;
+                b.red = red_of(ctx, SC_TMP + 7, EPI_STORE);
+                hop<double>(ctx, false, HM_SCHUR_W, true, b);
+                if (op == EOFA_OP_SCHUR) {
+                    HIPCHK(hipMemcpyAsync(o.h[1], W.w, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+                    break;
+                }
+                src = W.w;
+            } else {
+                HIPCHK(launch_site<double>(Ns, true, src, W.wt, Ad, ctx->g.Vh, ctx->st));
+            }
+            auto c = hop_args<double>(ctx, 0);
+            c.in = W.wt; c.out = W.at; c.opA = Ad; c.cz = 1.0; c.caux = 0.0;
+            hop<double>(ctx, true, HM_SITE, false, c);
+            auto d = hop_args<double>(ctx, 1);
+            d.in = W.at; d.out = o.h[1]; d.aux = src; d.caux = 1.0; d.cz = -0.25;
+            hop<double>(ctx, true, HM_LIN, false, d);
+            break;
+        }
+        default:
+            REQUIRE(false, EOFA_EINVAL, "unknown op");
+        }
+        // write back; H_T = gamma_5 R5 D_T reflects in s and flips the lower spins
+        for (int par = 0; par < 2; par++)
+            HIPCHK(launch_unpack5<double>(o.h[par], (cd*)out, ctx->g, par, Ns, op == EOFA_OP_HT ? 1 : 0, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        (void)nh;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_hop_timing(eofa_ctx* ctx, int enable, double* ms, long* launches, double* bytes) {
+    return guarded(ctx, [&]() -> eofa_status {
+        collect_timing(ctx);
+        ctx->timing = enable != 0;
+        if (ms) *ms = ctx->hop_ms;
+        if (launches) *launches = ctx->hop_launches;
+        if (bytes) *bytes = ctx->hop_bytes;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_hop_timing_reset(eofa_ctx* ctx) {
+    return guarded(ctx, [&]() -> eofa_status {
+        collect_timing(ctx);
+        ctx->hop_ms = 0;
+        ctx->hop_launches = 0;
+        ctx->hop_bytes = 0;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_set_precond(eofa_ctx* ctx, const void* weights_dev, size_t bytes) {
+    return guarded(ctx, [&]() -> eofa_status {
+        (void)weights_dev; (void)bytes;
+        REQUIRE(false, EOFA_ENOTIMPL, "learned preconditioner not available in this build");
+        return EOFA_OK;
+    });
+}
+
+const char* eofa_last_error(const eofa_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void eofa_destroy(eofa_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& kv : ctx->tabs) (void)hipFree(kv.second);
+    for (int p = 0; p < 2; p++) {
+        if (ctx->U[p]) (void)hipFree(ctx->U[p]);
+        if (ctx->Uf[p]) (void)hipFree(ctx->Uf[p]);
+    }
+    if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
+    if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->counter) (void)hipFree(ctx->counter);
+    if (ctx->scal) (void)hipFree(ctx->scal);
+    if (ctx->hscal) (void)hipHostFree(ctx->hscal);
+    for (auto& e : ctx->ev_pool) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    delete ctx;
+}
+
+}  // extern "C"

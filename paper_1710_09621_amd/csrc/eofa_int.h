@@ -1,0 +1,57 @@
+// Internal declarations shared by the kernels (kernels.hip) and the host runtime (eofa.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "eofa_dev.h"
+
+namespace eofa {
+
+enum : int { HM_LIN = 0, HM_SITE = 1, HM_SCHUR_W = 2, HM_SCHUR_Q = 3, HM_DT = 4, HM_DW = 5 };
+
+template <typename R> struct HopArgs {
+    Geom g;
+    int par;                  // parity of the output sites
+    const cpx<R>* in;         // half field of parity 1 - par (the hop input)
+    const cpx<R>* Uown;       // packed links of parity par
+    const cpx<R>* Uoth;       // packed links of parity 1 - par
+    cpx<R>* out;
+    cpx<R>* out2;
+    const cpx<R>* aux;        // parity par
+    const cpx<R>* aux2;       // parity par
+    const cpx<R>* self;       // parity par (diagonal term of D_T / D_w)
+    const SiteOp* opA;
+    const SiteOp* opB;
+    R cz, caux, diag;
+    const double* scal;       // device scalars (alpha)
+    const double* done;       // early-exit flag for graph replays (may be null)
+    Red red;
+};
+
+template <typename R> hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st);
+template <typename R> hipError_t launch_site(int Ns, bool dag, const cpx<R>* in, cpx<R>* out, const SiteOp* op, int Vh,
+                                             hipStream_t st);
+template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, const double* scal, size_t n,
+                                              hipStream_t st);
+template <typename R> hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red,
+                                              hipStream_t st);
+template <typename R> hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st);
+hipError_t launch_convert_d2f(const cd* in, cpx<float>* out, size_t n, hipStream_t st);
+hipError_t launch_convert_f2d(const cpx<float>* in, cd* out, size_t n, hipStream_t st);
+hipError_t launch_accum_f(cd* xhi, const cpx<float>* xlo, size_t n, hipStream_t st);
+template <typename R> hipError_t launch_pack5(const cd* canon, cpx<R>* half, const Geom& g, int par, int Ns, int refl,
+                                              hipStream_t st);
+template <typename R> hipError_t launch_unpack5(const cpx<R>* half, cd* canon, const Geom& g, int par, int Ns, int refl,
+                                                hipStream_t st);
+template <typename R> hipError_t launch_pack_links(const cd* U, cpx<R>* Up, const Geom& g, int par, double tbc,
+                                                   hipStream_t st);
+hipError_t launch_source(const cd* phi, cd* half, const Geom& g, int par, int Ns, int chir, const double* coef,
+                         hipStream_t st);
+hipError_t launch_combine(const cd* phi, const cd* xh, cd* out, const Geom& g, int par, int Ns, int chir, double ck,
+                          const double* Om, int accumulate, const Red& red, hipStream_t st);
+
+// ---- site-local operator tables (sitetab.cpp)
+enum SiteKind : int { SK_AINV = 0, SK_AINV_DAG = 1, SK_M = 2, SK_M_DAG = 3 };
+// Fill op with the tables of A_T^{-1}, A_T^{-dag}, M or M^T for masses (mp, mm).
+void build_site_op(SiteOp& op, SiteKind kind, int Ns, double m0, const double* omega, double mp, double mm);
+
+}  // namespace eofa

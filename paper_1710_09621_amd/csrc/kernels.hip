@@ -1,0 +1,485 @@
+// gfx950 kernels of the EOFA / optimal-DWF solve path: the fused even-odd hop with its
+// site-local epilogues, BLAS-1 steps with deterministic FP64 reductions, and the
+// pack / source / combine kernels at the canonical boundary.
+#include "eofa_int.h"
+
+namespace eofa {
+
+// ===================================================================== the fused hop
+// One launch computes, for every (4D site x of parity par, slice s):
+//   z = sum_mu [(1 - S gamma_mu) U_mu(x) in(x+mu, s) + (1 + S gamma_mu) U_mu(x-mu)^dag in(x-mu, s)]
+// (S = +1 normal hop, S = -1 for gamma_5 hop gamma_5 when DAG) and then one epilogue:
+//   HM_LIN     out = caux*aux + cz*z
+//   HM_SITE    out = A (caux*aux + cz*z)                       A = site op (A_T^{-1} or A_T^{-dag})
+//   HM_SCHUR_W out = w = caux*aux + cz*A(z);  out2 = B(w);  sum |w|^2 -> alpha   (Dhat p, A^{-dag} Dhat p)
+//   HM_SCHUR_Q q = caux*aux + cz*z;  out = aux2 - alpha*q;  sum |out|^2 -> beta  (CG residual update)
+//   HM_DT      out = caux*aux + cz*((4-m0) self + A(self) - z/2)                (D_T, A = M or M^T)
+//   HM_DW      out = caux*aux + cz*((4-m0) self - z/2)                          (D_w on every slice)
+template <int NS, bool DAG, int MU, typename R>
+__device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict__ in,
+                                       const cpx<R>* __restrict__ Uown, const cpx<R>* __restrict__ Uoth,
+                                       int cb, const int nb[8], int s) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    {
+        const cpx<R>* src = in + (size_t)nb[2 * MU] * 12 * NS + s;
+        cpx<R> p[12];
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+        cpx<R> h[6], w[6], U[9];
+        project<MU, SF>(p, h);
+        const cpx<R>* up = Uown + ((size_t)cb * 4 + MU) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; k++) U[k] = up[k];
+        link_mul<false>(U, h, w);
+        reconstruct<MU, SF>(acc, w);
+    }
+    {
+        const int n = nb[2 * MU + 1];
+        const cpx<R>* src = in + (size_t)n * 12 * NS + s;
+        cpx<R> p[12];
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+        cpx<R> h[6], w[6], U[9];
+        project<MU, SB>(p, h);
+        const cpx<R>* up = Uoth + ((size_t)n * 4 + MU) * 9;
+#pragma unroll
+        for (int k = 0; k < 9; k++) U[k] = up[k];
+        link_mul<true>(U, h, w);
+        reconstruct<MU, SB>(acc, w);
+    }
+}
+
+#ifndef HOP_FENCE
+#define HOP_FENCE() __builtin_amdgcn_sched_barrier(0)
+#endif
+#ifndef HOP_WAVES
+#define HOP_WAVES 2
+#endif
+// v += c * aux[j * NS] for the 12 components (aux already offset to this lane's element)
+template <int NS, typename R>
+__device__ __forceinline__ void add_aux_ns(cpx<R> v[12], const cpx<R>* __restrict__ aux, R c) {
+#pragma unroll
+    for (int j = 0; j < 12; j++) {
+        cpx<R> t = aux[j * NS];
+        v[j].x = fma(c, t.x, v[j].x);
+        v[j].y = fma(c, t.y, v[j].y);
+    }
+}
+#define add_aux(v, ptr, c) add_aux_ns<NS>(v, ptr, c)
+
+template <int NS, bool DAG, int MODE, bool RED, typename R>
+__global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
+    if (a.done && *a.done != 0.0) return;
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int s = lane & (NS - 1);
+    int cb = tid / NS;
+    const bool valid = cb < a.g.Vh;
+    if (!valid) cb = a.g.Vh - 1;  // keep every lane of a group active for the lane exchanges
+    int nb[8];
+    neighbours(a.g, cb, a.par, nb);
+    cpx<R> z[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) z[j] = {0, 0};
+    hop_mu<NS, DAG, 0>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 1>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 2>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 3>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
+
+    const size_t base = (size_t)cb * 12 * NS + s;
+    double nrm = 0.0;
+    cpx<R> v[12];
+    if constexpr (MODE == HM_LIN || MODE == HM_SITE) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) v[j] = cscale(a.cz, z[j]);
+        if (a.aux) add_aux(v, a.aux + base, a.caux);
+        if constexpr (MODE == HM_SITE) site_op<NS, DAG>(v, *a.opA, s, lane);
+    } else if constexpr (MODE == HM_SCHUR_W) {
+        site_op<NS, false>(z, *a.opA, s, lane);
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            cpx<R> t = a.aux[base + j * NS];
+            v[j].x = fma(a.cz, z[j].x, a.caux * t.x);
+            v[j].y = fma(a.cz, z[j].y, a.caux * t.y);
+        }
+    } else if constexpr (MODE == HM_SCHUR_Q) {
+        const R alpha = (R)a.scal[SC_ALPHA];
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            cpx<R> w = a.aux[base + j * NS], r = a.aux2[base + j * NS];
+            R qx = fma(a.cz, z[j].x, a.caux * w.x), qy = fma(a.cz, z[j].y, a.caux * w.y);
+            v[j].x = fma(-alpha, qx, r.x);
+            v[j].y = fma(-alpha, qy, r.y);
+        }
+    } else if constexpr (MODE == HM_DT || MODE == HM_DW) {
+        cpx<R> d[12];
+#pragma unroll
+        for (int j = 0; j < 12; j++) d[j] = a.self[base + j * NS];
+        cpx<R> m[12];
+#pragma unroll
+        for (int j = 0; j < 12; j++) m[j] = d[j];
+        if constexpr (MODE == HM_DT) site_op<NS, DAG>(m, *a.opA, s, lane);
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            R tx = a.diag * d[j].x - (R)0.5 * z[j].x, ty = a.diag * d[j].y - (R)0.5 * z[j].y;
+            if constexpr (MODE == HM_DT) { tx += m[j].x; ty += m[j].y; }
+            v[j] = {a.cz * tx, a.cz * ty};
+        }
+        if (a.aux) add_aux(v, a.aux + base, a.caux);
+    }
+    if (valid) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) a.out[base + j * NS] = v[j];
+    }
+    if constexpr (MODE == HM_SCHUR_W) {
+        if constexpr (RED) {
+#pragma unroll
+            for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+        }
+        site_op<NS, true>(v, *a.opB, s, lane);
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < 12; j++) a.out2[base + j * NS] = v[j];
+        }
+    } else if constexpr (RED) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+    }
+    if constexpr (RED) {
+        __shared__ double lds[4];
+        if (!valid) nrm = 0.0;
+        finish_sum(a.red, block_sum256(nrm, lds));
+    }
+}
+
+// ===================================================================== site-local op only
+template <int NS, bool DAG, typename R>
+__global__ __launch_bounds__(256) void k_site(const cpx<R>* __restrict__ in, cpx<R>* __restrict__ out,
+                                              const SiteOp* __restrict__ op, int Vh) {
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int s = lane & (NS - 1);
+    int cb = tid / NS;
+    const bool valid = cb < Vh;
+    if (!valid) cb = Vh - 1;
+    const size_t base = (size_t)cb * 12 * NS + s;
+    cpx<R> v[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) v[j] = in[base + j * NS];
+    site_op<NS, DAG>(v, *op, s, lane);
+    if (valid) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) out[base + j * NS] = v[j];
+    }
+}
+
+// ===================================================================== BLAS-1
+// CG step after the residual update: x += alpha p ; p = r + beta p   (alpha, beta on device)
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_xp(cpx<R>* __restrict__ x, cpx<R>* __restrict__ p,
+                                               const cpx<R>* __restrict__ r, const double* __restrict__ scal,
+                                               size_t n) {
+    const R alpha = (R)scal[SC_ALPHA], beta = (R)scal[SC_BETA];
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        cpx<R> pp = p[i], rr = r[i], xx = x[i];
+        xx.x = fma(alpha, pp.x, xx.x); xx.y = fma(alpha, pp.y, xx.y);
+        pp.x = fma(beta, pp.x, rr.x);  pp.y = fma(beta, pp.y, rr.y);
+        x[i] = xx; p[i] = pp;
+    }
+}
+
+// y = a*x + b*y, with an optional |y|^2 reduction
+template <typename R, bool RED>
+__global__ __launch_bounds__(256) void k_axpby(R a, const cpx<R>* __restrict__ x, R b, cpx<R>* __restrict__ y,
+                                               size_t n, Red red) {
+    double nrm = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        cpx<R> xx = x ? x[i] : cpx<R>{0, 0}, yy = y[i];
+        yy.x = fma(a, xx.x, b * yy.x); yy.y = fma(a, xx.y, b * yy.y);
+        y[i] = yy;
+        if constexpr (RED) nrm += (double)yy.x * yy.x + (double)yy.y * yy.y;
+    }
+    if constexpr (RED) {
+        __shared__ double lds[4];
+        finish_sum(red, block_sum256(nrm, lds));
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_norm2(const cpx<R>* __restrict__ x, size_t n, Red red) {
+    double nrm = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        cpx<R> xx = x[i];
+        nrm += (double)xx.x * xx.x + (double)xx.y * xx.y;
+    }
+    __shared__ double lds[4];
+    finish_sum(red, block_sum256(nrm, lds));
+}
+
+// precision conversion: out = (To) in
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void k_convert(const cpx<Ti>* __restrict__ in, cpx<To>* __restrict__ out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        cpx<Ti> v = in[i];
+        out[i] = {(To)v.x, (To)v.y};
+    }
+}
+
+// x_hi += (double) x_lo
+template <typename R>
+__global__ __launch_bounds__(256) void k_accum_lo(cd* __restrict__ xhi, const cpx<R>* __restrict__ xlo, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        cpx<R> v = xlo[i];
+        cd h = xhi[i];
+        xhi[i] = {h.x + (double)v.x, h.y + (double)v.y};
+    }
+}
+
+// ===================================================================== boundary kernels
+// canonical index of (s, lex site, j): ((s * V + lex) * 12 + j)
+__device__ __forceinline__ void cb_to_lex(const Geom& g, int cb, int par, int& lex) {
+    int xh = cb % g.Lxh;
+    int r = cb / g.Lxh;
+    int y = r % g.Ly; r /= g.Ly;
+    int z = r % g.Lz;
+    int t = r / g.Lz;
+    int x = 2 * xh + ((y + z + t + par) & 1);
+    lex = x + g.Lx * (y + g.Ly * (z + g.Lz * t));
+}
+
+// canonical 5D (complex128) <-> internal half field of parity par.  One thread per (cb, j, s).
+// refl != 0 applies R5 gamma_5 on the way: half(s) = gamma_5 canon(Ns - 1 - s), gamma_5 = diag(1, 1, -1, -1).
+template <typename R>
+__global__ __launch_bounds__(256) void k_pack5(const cd* __restrict__ canon, cpx<R>* __restrict__ half, Geom g,
+                                               int par, int Ns, int refl) {
+    const size_t n = (size_t)g.Vh * 12 * Ns;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        int s = (int)(i % Ns);
+        int j = (int)((i / Ns) % 12);
+        int cb = (int)(i / ((size_t)12 * Ns));
+        int lex;
+        cb_to_lex(g, cb, par, lex);
+        int sc = refl ? Ns - 1 - s : s;
+        cd v = canon[((size_t)sc * (2 * (size_t)g.Vh) + lex) * 12 + j];
+        double sg = (refl && j >= 6) ? -1.0 : 1.0;
+        half[i] = {(R)(sg * v.x), (R)(sg * v.y)};
+    }
+}
+
+// refl != 0 applies gamma_5 R5 on the way: canon(Ns - 1 - s) = gamma_5 half(s).
+template <typename R>
+__global__ __launch_bounds__(256) void k_unpack5(const cpx<R>* __restrict__ half, cd* __restrict__ canon, Geom g,
+                                                 int par, int Ns, int refl) {
+    const size_t n = (size_t)g.Vh * 12 * Ns;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        int s = (int)(i % Ns);
+        int j = (int)((i / Ns) % 12);
+        int cb = (int)(i / ((size_t)12 * Ns));
+        int lex;
+        cb_to_lex(g, cb, par, lex);
+        cpx<R> v = half[i];
+        int sc = refl ? Ns - 1 - s : s;
+        double sg = (refl && j >= 6) ? -1.0 : 1.0;
+        canon[((size_t)sc * (2 * (size_t)g.Vh) + lex) * 12 + j] = {sg * (double)v.x, sg * (double)v.y};
+    }
+}
+
+// links: canonical [lex][mu][3][3] -> packed [par][cb][mu][9], t-boundary phase folded into U_t(x_t = Lt-1)
+template <typename R>
+__global__ __launch_bounds__(256) void k_pack_links(const cd* __restrict__ U, cpx<R>* __restrict__ Up, Geom g,
+                                                    int par, double tbc) {
+    const size_t n = (size_t)g.Vh * 36;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        int k = (int)(i % 9);
+        int mu = (int)((i / 9) % 4);
+        int cb = (int)(i / 36);
+        int lex;
+        cb_to_lex(g, cb, par, lex);
+        cd v = U[((size_t)lex * 4 + mu) * 9 + k];
+        int t = lex / (g.Lx * g.Ly * g.Lz);
+        if (mu == 3 && t == g.Lt - 1) { v.x *= tbc; v.y *= tbc; }
+        Up[i] = {(R)v.x, (R)v.y};
+    }
+}
+
+// EOFA source: c_s = coef[s] * P_chir phi at every site of parity par (coef[s] = chir * Om_{Ns-1-s},
+// i.e. c = R5 gamma_5 (Om (x) P_chir phi)).  One thread per (cb, j, s).
+__global__ __launch_bounds__(256) void k_source(const cd* __restrict__ phi, cd* __restrict__ half, Geom g, int par,
+                                                int Ns, int chir, const double* __restrict__ coef) {
+    const size_t n = (size_t)g.Vh * 12 * Ns;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        int s = (int)(i % Ns);
+        int j = (int)((i / Ns) % 12);
+        int cb = (int)(i / ((size_t)12 * Ns));
+        int lex;
+        cb_to_lex(g, cb, par, lex);
+        int spin = j / 3;
+        bool keep = (chir > 0) ? (spin < 2) : (spin >= 2);
+        cd v = phi[(size_t)lex * 12 + j];
+        double c = keep ? coef[s] : 0.0;
+        half[i] = {c * v.x, c * v.y};
+    }
+}
+
+// EOFA combine: out = P_chir phi + ck * sum_s Om_s P_chir x_s on the sites of parity par, and the
+// partial sums of Re phi^dag out.  One thread per (cb, j).
+__global__ __launch_bounds__(256) void k_combine(const cd* __restrict__ phi, const cd* __restrict__ xh, cd* __restrict__ out,
+                                                 Geom g, int par, int Ns, int chir, double ck,
+                                                 const double* __restrict__ Om, int accumulate, Red red) {
+    const size_t n = (size_t)g.Vh * 12;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        int j = (int)(i % 12);
+        int cb = (int)(i / 12);
+        int lex;
+        cb_to_lex(g, cb, par, lex);
+        int spin = j / 3;
+        bool keep = (chir > 0) ? (spin < 2) : (spin >= 2);
+        cd ph = phi[(size_t)lex * 12 + j];
+        cd o = {0.0, 0.0};
+        if (keep) {
+            double sx = 0.0, sy = 0.0;
+            const cd* src = xh + ((size_t)cb * 12 + j) * Ns;
+            for (int s = 0; s < Ns; s++) { sx = fma(Om[s], src[s].x, sx); sy = fma(Om[s], src[s].y, sy); }
+            o = {ph.x + ck * sx, ph.y + ck * sy};
+        }
+        cd* dst = out + (size_t)lex * 12 + j;
+        if (accumulate) { cd t = *dst; o.x += t.x; o.y += t.y; }
+        *dst = o;
+        // Re phi^dag (this action's part only)
+        if (keep) acc += ph.x * o.x + ph.y * o.y;
+    }
+    __shared__ double lds[4];
+    finish_sum(red, block_sum256(acc, lds));
+}
+
+// 4D canonical field zero/copy helpers are done with hipMemsetAsync / hipMemcpyAsync.
+
+// ===================================================================== launchers
+static inline int nblk(size_t n) {
+    size_t b = (n + 255) / 256;
+    return (int)(b > 65535 * 8 ? 65535 * 8 : b);
+}
+
+#define NS_SWITCH(NSV, ...)                                            \
+    switch (NSV) {                                                     \
+    case 4: { constexpr int NS = 4; __VA_ARGS__; break; }              \
+    case 8: { constexpr int NS = 8; __VA_ARGS__; break; }              \
+    case 16: { constexpr int NS = 16; __VA_ARGS__; break; }            \
+    case 32: { constexpr int NS = 32; __VA_ARGS__; break; }            \
+    default: return hipErrorInvalidValue;                              \
+    }
+
+template <typename R>
+hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st) {
+    const size_t nthreads = (size_t)a.g.Vh * Ns;
+    const int grid = (int)((nthreads + 255) / 256);
+#define HOP_L(D, M, RD) hipLaunchKernelGGL((k_hop<NS, D, M, RD, R>), dim3(grid), dim3(256), 0, st, a)
+#define HOP_MODES(D)                                                                        \
+    switch (mode) {                                                                         \
+    case HM_LIN: if (red) HOP_L(D, HM_LIN, true); else HOP_L(D, HM_LIN, false); break;     \
+    case HM_SITE: if (red) HOP_L(D, HM_SITE, true); else HOP_L(D, HM_SITE, false); break;  \
+    case HM_SCHUR_W: HOP_L(D, HM_SCHUR_W, true); break;                                     \
+    case HM_SCHUR_Q: HOP_L(D, HM_SCHUR_Q, true); break;                                     \
+    case HM_DT: if (red) HOP_L(D, HM_DT, true); else HOP_L(D, HM_DT, false); break;        \
+    case HM_DW: HOP_L(D, HM_DW, false); break;                                              \
+    default: return hipErrorInvalidValue;                                                   \
+    }
+    NS_SWITCH(Ns, if (dag) { HOP_MODES(true) } else { HOP_MODES(false) });
+#undef HOP_MODES
+#undef HOP_L
+    return hipGetLastError();
+}
+template hipError_t launch_hop<double>(int, bool, int, bool, const HopArgs<double>&, hipStream_t);
+template hipError_t launch_hop<float>(int, bool, int, bool, const HopArgs<float>&, hipStream_t);
+
+template <typename R>
+hipError_t launch_site(int Ns, bool dag, const cpx<R>* in, cpx<R>* out, const SiteOp* op, int Vh, hipStream_t st) {
+    const int grid = (int)(((size_t)Vh * Ns + 255) / 256);
+    NS_SWITCH(Ns, if (dag) hipLaunchKernelGGL((k_site<NS, true, R>), dim3(grid), dim3(256), 0, st, in, out, op, Vh);
+              else hipLaunchKernelGGL((k_site<NS, false, R>), dim3(grid), dim3(256), 0, st, in, out, op, Vh));
+    return hipGetLastError();
+}
+template hipError_t launch_site<double>(int, bool, const cd*, cd*, const SiteOp*, int, hipStream_t);
+template hipError_t launch_site<float>(int, bool, const cpx<float>*, cpx<float>*, const SiteOp*, int, hipStream_t);
+
+template <typename R>
+hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, const double* scal, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_cg_xp<R>), dim3(nblk(n)), dim3(256), 0, st, x, p, r, scal, n);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_xp<double>(cd*, cd*, const cd*, const double*, size_t, hipStream_t);
+template hipError_t launch_cg_xp<float>(cpx<float>*, cpx<float>*, const cpx<float>*, const double*, size_t, hipStream_t);
+
+template <typename R>
+hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red, hipStream_t st) {
+    if (red) hipLaunchKernelGGL((k_axpby<R, true>), dim3(nblk(n)), dim3(256), 0, st, a, x, b, y, n, *red);
+    else hipLaunchKernelGGL((k_axpby<R, false>), dim3(nblk(n)), dim3(256), 0, st, a, x, b, y, n, Red{});
+    return hipGetLastError();
+}
+template hipError_t launch_axpby<double>(double, const cd*, double, cd*, size_t, const Red*, hipStream_t);
+template hipError_t launch_axpby<float>(float, const cpx<float>*, float, cpx<float>*, size_t, const Red*, hipStream_t);
+
+template <typename R>
+hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st) {
+    hipLaunchKernelGGL((k_norm2<R>), dim3(nblk(n)), dim3(256), 0, st, x, n, red);
+    return hipGetLastError();
+}
+template hipError_t launch_norm2<double>(const cd*, size_t, const Red&, hipStream_t);
+template hipError_t launch_norm2<float>(const cpx<float>*, size_t, const Red&, hipStream_t);
+
+hipError_t launch_convert_d2f(const cd* in, cpx<float>* out, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_convert_f2d(const cpx<float>* in, cd* out, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nblk(n)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+hipError_t launch_accum_f(cd* xhi, const cpx<float>* xlo, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL((k_accum_lo<float>), dim3(nblk(n)), dim3(256), 0, st, xhi, xlo, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_pack5(const cd* canon, cpx<R>* half, const Geom& g, int par, int Ns, int refl, hipStream_t st) {
+    hipLaunchKernelGGL((k_pack5<R>), dim3(nblk((size_t)g.Vh * 12 * Ns)), dim3(256), 0, st, canon, half, g, par, Ns, refl);
+    return hipGetLastError();
+}
+template hipError_t launch_pack5<double>(const cd*, cd*, const Geom&, int, int, int, hipStream_t);
+template hipError_t launch_pack5<float>(const cd*, cpx<float>*, const Geom&, int, int, int, hipStream_t);
+
+template <typename R>
+hipError_t launch_unpack5(const cpx<R>* half, cd* canon, const Geom& g, int par, int Ns, int refl, hipStream_t st) {
+    hipLaunchKernelGGL((k_unpack5<R>), dim3(nblk((size_t)g.Vh * 12 * Ns)), dim3(256), 0, st, half, canon, g, par, Ns, refl);
+    return hipGetLastError();
+}
+template hipError_t launch_unpack5<double>(const cd*, cd*, const Geom&, int, int, int, hipStream_t);
+template hipError_t launch_unpack5<float>(const cpx<float>*, cd*, const Geom&, int, int, int, hipStream_t);
+
+template <typename R>
+hipError_t launch_pack_links(const cd* U, cpx<R>* Up, const Geom& g, int par, double tbc, hipStream_t st) {
+    hipLaunchKernelGGL((k_pack_links<R>), dim3(nblk((size_t)g.Vh * 36)), dim3(256), 0, st, U, Up, g, par, tbc);
+    return hipGetLastError();
+}
+template hipError_t launch_pack_links<double>(const cd*, cd*, const Geom&, int, double, hipStream_t);
+template hipError_t launch_pack_links<float>(const cd*, cpx<float>*, const Geom&, int, double, hipStream_t);
+
+hipError_t launch_source(const cd* phi, cd* half, const Geom& g, int par, int Ns, int chir, const double* coef,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_source, dim3(nblk((size_t)g.Vh * 12 * Ns)), dim3(256), 0, st, phi, half, g, par, Ns, chir, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const cd* phi, const cd* xh, cd* out, const Geom& g, int par, int Ns, int chir, double ck,
+                          const double* Om, int accumulate, const Red& red, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine, dim3(nblk((size_t)g.Vh * 12)), dim3(256), 0, st, phi, xh, out, g, par, Ns, chir, ck,
+                       Om, accumulate, red);
+    return hipGetLastError();
+}
+
+}  // namespace eofa

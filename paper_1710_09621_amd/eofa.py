@@ -1,0 +1,245 @@
+"""Python binding of the gfx950 EOFA library (libeofa.so) over its C ABI.
+
+Argument marshalling only: every step of the solve runs in the HIP library.  Torch
+supplies device memory and the stream.  There is no CPU fallback: if the library is
+missing or no GPU is visible, every call raises.
+
+Canonical layouts (torch.complex128 on the GPU), dims = (Lx, Ly, Lz, Lt):
+  links (Lt, Lz, Ly, Lx, 4, 3, 3); 4D (Lt, Lz, Ly, Lx, 4, 3); 5D (Ns, Lt, Lz, Ly, Lx, 4, 3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeofa.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
+PC_NONE, PC_LEARNED = 0, 1
+OPS = dict(DW=0, HOP=1, DT=2, DT_DAG=3, HT=4, AT_INV=5, SCHUR=6, SCHUR_DAG=7, SCHUR_NORMAL=8)
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "ESTATE", -6: "ENOTIMPL"}
+
+
+class EofaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("prec", C.c_int), ("pc", C.c_int),
+                ("reliable_delta", C.c_double), ("use_graph", C.c_int), ("check_every", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("op_applies", C.c_int), ("reliable_updates", C.c_int),
+                ("fell_back", C.c_int), ("true_rel_resid", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def params(tol=1e-10, max_iter=100000, prec=FP64, pc=PC_NONE, reliable_delta=0.0, use_graph=0, check_every=0):
+    return SolveParams(tol, max_iter, prec, pc, reliable_delta, use_graph, check_every)
+
+
+def load():
+    """Load libeofa.so (built beforehand by build()); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_1710_09621_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D, Z = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+    PP = C.POINTER(C.c_void_p)
+    sig = {
+        "eofa_create": [C.POINTER(C.c_void_p), C.POINTER(C.c_int), I, D, C.POINTER(C.c_double), I, P],
+        "eofa_workspace_size": [P, C.POINTER(SolveParams), I, C.POINTER(C.c_size_t)],
+        "eofa_set_workspace": [P, P, Z],
+        "eofa_set_gauge": [P, P],
+        "eofa_hinv": [P, D, D, P, P, C.POINTER(C.c_double), C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "eofa_chiral_action": [P, I, D, D, D, P, P, C.POINTER(C.c_double), C.POINTER(SolveParams),
+                               C.POINTER(SolveInfo)],
+        "eofa_chiral_action_batch": [P, I, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), PP, PP, C.POINTER(C.c_double),
+                                     C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "eofa_hinv_batch": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double), PP, PP, C.POINTER(C.c_double),
+                            C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "eofa_solve_ht": [P, D, D, P, P, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "eofa_apply": [P, I, D, D, P, P, I],
+        "eofa_hop_timing": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)],
+        "eofa_hop_timing_reset": [P],
+        "eofa_set_precond": [P, P, Z],
+        "eofa_last_error": [P],
+        "eofa_destroy": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.eofa_last_error.restype = C.c_char_p
+    lib.eofa_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the library exports (for the ABI test)."""
+    lib = load()
+    return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
+                        "eofa_chiral_action", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
+                        "eofa_apply", "eofa_hop_timing", "eofa_hop_timing_reset", "eofa_set_precond",
+                        "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Result:
+    out: object
+    S: float
+    info: list
+
+
+class Context:
+    """One lattice + weights + stream.  Not thread-safe."""
+
+    def __init__(self, dims, Ns, m0, omega, t_bc=-1, device="cuda:0", workspace=True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the EOFA library has no CPU path")
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device(device)
+        self.dims = tuple(int(d) for d in dims)
+        self.Ns = int(Ns)
+        self.m0 = float(m0)
+        self.omega = np.ascontiguousarray(omega, dtype=np.float64)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        d = (C.c_int * 4)(*self.dims)
+        om = self.omega.ctypes.data_as(C.POINTER(C.c_double))
+        st = self.lib.eofa_create(C.byref(h), d, self.Ns, self.m0, om, int(t_bc), C.c_void_p(self.stream.cuda_stream))
+        if st != OK:
+            raise EofaError(st, "eofa_create failed (see stderr)")
+        self.h = h
+        self._ws = None
+        self._use_ws = workspace
+        Lx, Ly, Lz, Lt = self.dims
+        self.shape4 = (Lt, Lz, Ly, Lx, 4, 3)
+        self.shape5 = (self.Ns,) + self.shape4
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.lib:
+                self.lib.eofa_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != OK:
+            msg = self.lib.eofa_last_error(self.h)
+            raise EofaError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def _prep_ws(self, p, nrhs=1):
+        if not self._use_ws:
+            return
+        n = C.c_size_t()
+        self._check(self.lib.eofa_workspace_size(self.h, C.byref(p), nrhs, C.byref(n)), "workspace_size")
+        if self._ws is None or self._ws.numel() < n.value:
+            self._ws = None
+            self._ws = self.torch.empty(n.value + 256, dtype=self.torch.uint8, device=self.device)
+            addr = self._ws.data_ptr()
+            off = (-addr) % 256
+            self._check(self.lib.eofa_set_workspace(self.h, C.c_void_p(addr + off), n.value), "set_workspace")
+
+    def _c128(self, t, shape):
+        torch = self.torch
+        if isinstance(t, np.ndarray):
+            t = torch.from_numpy(np.ascontiguousarray(t, dtype=np.complex128))
+        t = t.to(device=self.device, dtype=torch.complex128).contiguous()
+        assert tuple(t.shape) == tuple(shape), (tuple(t.shape), shape)
+        return t
+
+    def set_gauge(self, U):
+        Lx, Ly, Lz, Lt = self.dims
+        U = self._c128(U, (Lt, Lz, Ly, Lx, 4, 3, 3))
+        self._check(self.lib.eofa_set_gauge(self.h, _ptr(U)), "set_gauge")
+
+    def apply(self, op, x, mp=1.0, mm=1.0, prec=FP64):
+        x = self._c128(x, self.shape5)
+        out = self.torch.empty_like(x)
+        self._prep_ws(params())
+        self._check(self.lib.eofa_apply(self.h, OPS[op] if isinstance(op, str) else int(op), float(mp), float(mm),
+                                        _ptr(x), _ptr(out), int(prec)), f"apply({op})")
+        return out
+
+    def solve_ht(self, b, mp, mm, p=None):
+        p = p or params()
+        b = self._c128(b, self.shape5)
+        x = self.torch.empty_like(b)
+        self._prep_ws(p)
+        info = SolveInfo()
+        st = self.lib.eofa_solve_ht(self.h, float(mp), float(mm), _ptr(b), _ptr(x), C.byref(p), C.byref(info))
+        self._check(st, "solve_ht")
+        return x, info.as_dict()
+
+    def chiral_action(self, chir, m3, m4, mo, phi, p=None):
+        p = p or params()
+        phi = self._c128(phi, self.shape4)
+        out = self.torch.empty_like(phi)
+        self._prep_ws(p)
+        S = C.c_double()
+        info = SolveInfo()
+        st = self.lib.eofa_chiral_action(self.h, int(chir), float(m3), float(m4), float(mo), _ptr(phi), _ptr(out),
+                                         C.byref(S), C.byref(p), C.byref(info))
+        self._check(st, "chiral_action")
+        return Result(out, S.value, [info.as_dict()])
+
+    def hinv(self, phi, m_lo, m_hi, p=None):
+        p = p or params()
+        phi = self._c128(phi, self.shape4)
+        out = self.torch.empty_like(phi)
+        self._prep_ws(p)
+        S = C.c_double()
+        info = (SolveInfo * 2)()
+        st = self.lib.eofa_hinv(self.h, float(m_lo), float(m_hi), _ptr(phi), _ptr(out), C.byref(S), C.byref(p), info)
+        self._check(st, "hinv")
+        return Result(out, S.value, [i.as_dict() for i in info])
+
+    def chiral_action_batch(self, actions, phis, p=None):
+        """actions: list of (chir, m3, m4, mo); phis: list of 4D tensors."""
+        p = p or params()
+        n = len(actions)
+        phis = [self._c128(f, self.shape4) for f in phis]
+        outs = [self.torch.empty_like(f) for f in phis]
+        self._prep_ws(p, n)
+        chir = (C.c_int * n)(*[int(a[0]) for a in actions])
+        m3 = (C.c_double * n)(*[float(a[1]) for a in actions])
+        m4 = (C.c_double * n)(*[float(a[2]) for a in actions])
+        mo = (C.c_double * n)(*[float(a[3]) for a in actions])
+        pin = (C.c_void_p * n)(*[f.data_ptr() for f in phis])
+        pout = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        S = (C.c_double * n)()
+        info = (SolveInfo * n)()
+        st = self.lib.eofa_chiral_action_batch(self.h, n, chir, m3, m4, mo, pin, pout, S, C.byref(p), info)
+        self._check(st, "chiral_action_batch")
+        return [Result(outs[j], S[j], [info[j].as_dict()]) for j in range(n)]
+
+    def hop_timing(self, enable=True):
+        ms, n, b = C.c_double(), C.c_long(), C.c_double()
+        self._check(self.lib.eofa_hop_timing(self.h, int(enable), C.byref(ms), C.byref(n), C.byref(b)), "hop_timing")
+        return dict(ms=ms.value, launches=n.value, bytes=b.value)
+
+    def hop_timing_reset(self):
+        self._check(self.lib.eofa_hop_timing_reset(self.h), "hop_timing_reset")
