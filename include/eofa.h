@@ -160,6 +160,24 @@ eofa_status eofa_apply(eofa_ctx *ctx, int op, double m_plus, double m_minus, con
 eofa_status eofa_hop_timing(eofa_ctx *ctx, int enable, double *ms, long *launches, double *bytes);
 eofa_status eofa_hop_timing_reset(eofa_ctx *ctx);
 
+/* Diagnostic: nrep back-to-back launches of the fused even-odd hop with its A_T^{-1} epilogue
+ * (u = A_T^{-1} H_eo p, alternating parities, masses 0.01) on workspace buffers, in EOFA_FP64 or
+ * EOFA_MIXED_FP32 storage.  *ms = average device time per launch (HIP events), *alg_bytes =
+ * algorithmic HBM bytes of one launch (input and output half fields + 8 links per 4D site). */
+eofa_status eofa_dslash_bench(eofa_ctx *ctx, int prec, int nrep, double *ms, double *alg_bytes);
+
+/*
+ * Autotuner of the hop kernels' workgroup schedule (XCD-contiguous ranges, 3D tiling of the
+ * workgroup grid) for this lattice and storage precision: times every candidate with
+ * nrep launches of the fused hop (0: 4) and keeps the fastest for all later solves.
+ * sched_out[6] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb} for a persistent cache;
+ * *best_ms / *base_ms (may be NULL) the chosen and the linear-order launch times.
+ */
+eofa_status eofa_autotune(eofa_ctx *ctx, int prec, int nrep, int sched_out[6], double *best_ms,
+                          double *base_ms);
+/* Re-install a schedule returned by eofa_autotune (EINVAL if it does not fit this lattice). */
+eofa_status eofa_set_schedule(eofa_ctx *ctx, int prec, const int sched_in[6]);
+
 /* Learned preconditioner weights: the packed BF16 blob produced by eofa_cnn_* (see below). */
 eofa_status eofa_set_precond(eofa_ctx *ctx, const void *weights_dev, size_t bytes);
 

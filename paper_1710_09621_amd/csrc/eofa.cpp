@@ -42,7 +42,6 @@ struct eofa_ctx {
     size_t ws_bytes = 0;
     bool ws_owned = false;
     double* partials = nullptr;
-    unsigned* counter = nullptr;
     double* scal = nullptr;
     double* hscal = nullptr;  // pinned
     std::map<std::tuple<int, double, double>, SiteOp*> tabs;
@@ -54,6 +53,9 @@ struct eofa_ctx {
     double hop_ms = 0;
     long hop_launches = 0;
     double hop_bytes = 0;
+    // workgroup schedules of the hop kernels, per storage precision (0: FP64, 1: FP32); set by the autotuner
+    Sched sched[2] = {{0, 0, 1, 1, 1, 1}, {0, 0, 1, 1, 1, 1}};
+    double tuned_ms[2] = {0, 0};
 };
 
 namespace {
@@ -108,7 +110,7 @@ const SiteOp* site_tab(eofa_ctx* ctx, SiteKind kind, double mp, double mm) {
     return d;
 }
 
-Red red_of(eofa_ctx* ctx, int slot, int epi) { return Red{ctx->partials, ctx->counter, ctx->scal, slot, epi}; }
+Red red_of(eofa_ctx* ctx, int slot, int epi) { return Red{ctx->partials, ctx->scal, slot, epi}; }
 
 void sync_scal(eofa_ctx* ctx) {
     HIPCHK(hipMemcpyAsync(ctx->hscal, ctx->scal, sizeof(double) * SC_N, hipMemcpyDeviceToHost, ctx->st));
@@ -162,6 +164,20 @@ Work64 carve64(eofa_ctx* ctx) {
     return w;
 }
 
+struct Work32 {
+    cpx<float> *x, *r, *p, *u, *w, *wt, *at, *e0, *e1;
+};
+
+Work32 carve32(eofa_ctx* ctx) {
+    char* p = ctx->ws + work64_bytes(ctx);
+    const size_t hb = align_up(ctx->nh * sizeof(cpx<float>));
+    auto take = [&]() { cpx<float>* r = (cpx<float>*)p; p += hb; return r; };
+    Work32 w;
+    w.x = take(); w.r = take(); w.p = take(); w.u = take(); w.w = take(); w.wt = take(); w.at = take();
+    w.e0 = take(); w.e1 = take();
+    return w;
+}
+
 // ------------------------------------------------------------------ hop launch helpers
 template <typename R> HopArgs<R> hop_args(eofa_ctx* ctx, int par);
 template <> HopArgs<double> hop_args<double>(eofa_ctx* ctx, int par) {
@@ -170,6 +186,7 @@ template <> HopArgs<double> hop_args<double>(eofa_ctx* ctx, int par) {
     a.par = par;
     a.Uown = ctx->U[par];
     a.Uoth = ctx->U[1 - par];
+    a.sc = ctx->sched[0];
     a.diag = 4.0 - ctx->m0;
     a.scal = ctx->scal;
     return a;
@@ -180,6 +197,7 @@ template <> HopArgs<float> hop_args<float>(eofa_ctx* ctx, int par) {
     a.par = par;
     a.Uown = ctx->Uf[par];
     a.Uoth = ctx->Uf[1 - par];
+    a.sc = ctx->sched[1];
     a.diag = (float)(4.0 - ctx->m0);
     a.scal = ctx->scal;
     return a;
@@ -219,6 +237,35 @@ void collect_timing(eofa_ctx* ctx) {
     ctx->ev_used = 0;
 }
 
+// One CG iteration on Dhat^dag Dhat in storage/arithmetic type R (the four fused hops + BLAS).
+template <typename R>
+void cg_iteration(eofa_ctx* ctx, cpx<R>* x, cpx<R>* r, cpx<R>* p, cpx<R>* u, cpx<R>* w, cpx<R>* wt, cpx<R>* at,
+                  const SiteOp* Ai, const SiteOp* Ad) {
+    {
+        auto a = hop_args<R>(ctx, 0);
+        a.in = p; a.out = u; a.opA = Ai; a.cz = 1; a.caux = 0;
+        hop<R>(ctx, false, HM_SITE, false, a, sizeof(R) == 8);
+    }
+    {
+        auto a = hop_args<R>(ctx, 1);
+        a.in = u; a.out = w; a.out2 = wt; a.aux = p; a.opA = Ai; a.opB = Ad; a.cz = (R)-0.25; a.caux = 1;
+        a.red = red_of(ctx, 0, EPI_CG_W);
+        hop<R>(ctx, false, HM_SCHUR_W, true, a);
+    }
+    {
+        auto a = hop_args<R>(ctx, 0);
+        a.in = wt; a.out = at; a.opA = Ad; a.cz = 1; a.caux = 0;
+        hop<R>(ctx, true, HM_SITE, false, a);
+    }
+    {
+        auto a = hop_args<R>(ctx, 1);
+        a.in = at; a.out = r; a.aux = w; a.aux2 = r; a.cz = (R)-0.25; a.caux = 1;
+        a.red = red_of(ctx, 0, EPI_CG_R);
+        hop<R>(ctx, true, HM_SCHUR_Q, true, a);
+    }
+    HIPCHK(launch_cg_xp<R>(x, p, r, ctx->scal, ctx->nh, ctx->st));
+}
+
 // ------------------------------------------------------------------ FP64 CG on Dhat^dag Dhat
 struct CgOut {
     int iters = 0;
@@ -233,8 +280,7 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
     const size_t nh = ctx->nh;
     CgOut o;
     HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
-    double tol2 = tol_n * tol_n;
-    HIPCHK(hipMemcpyAsync(ctx->scal + SC_TOL2, &tol2, sizeof(double), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(launch_scal_set(ctx->scal, SC_TOL2, tol_n * tol_n, -1, 0, -1, 0, ctx->st));
     // r = Dhat^dag bh = bh - 1/4 g5 H_oe g5 A^{-dag} g5 H_eo g5 A^{-dag} bh ; p = r
     HIPCHK(launch_site<double>(ctx->Ns, true, W.bh, W.wt, Ad, ctx->g.Vh, ctx->st));
     {
@@ -254,30 +300,9 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
     if (ctx->hscal[SC_DONE] != 0.0) { o.converged = true; return o; }
     if (check_every <= 0) check_every = 1;
     while (o.iters < maxit) {
-        {   // K1: u = A^{-1} H_eo p
-            auto a = hop_args<double>(ctx, 0);
-            a.in = W.p; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
-            hop<double>(ctx, false, HM_SITE, false, a, true);
-        }
-        {   // K2: w = p - 1/4 A^{-1} H_oe u ; wt = A^{-dag} w ; |w|^2 -> alpha
-            auto a = hop_args<double>(ctx, 1);
-            a.in = W.u; a.out = W.w; a.out2 = W.wt; a.aux = W.p; a.opA = Ai; a.opB = Ad;
-            a.cz = -0.25; a.caux = 1.0;
-            a.red = red_of(ctx, 0, EPI_CG_W);
-            hop<double>(ctx, false, HM_SCHUR_W, true, a);
-        }
-        {   // K3: at = A^{-dag} g5 H_eo g5 wt
-            auto a = hop_args<double>(ctx, 0);
-            a.in = W.wt; a.out = W.at; a.opA = Ad; a.cz = 1.0; a.caux = 0.0;
-            hop<double>(ctx, true, HM_SITE, false, a);
-        }
-        {   // K4: r -= alpha (w - 1/4 g5 H_oe g5 at) ; |r|^2 -> beta
-            auto a = hop_args<double>(ctx, 1);
-            a.in = W.at; a.out = W.r; a.aux = W.w; a.aux2 = W.r; a.cz = -0.25; a.caux = 1.0;
-            a.red = red_of(ctx, 0, EPI_CG_R);
-            hop<double>(ctx, true, HM_SCHUR_Q, true, a);
-        }
-        HIPCHK(launch_cg_xp<double>(W.xcg, W.p, W.r, ctx->scal, nh, ctx->st));
+        // u = A^{-1} H_eo p ; w = Dhat p, wt = A^{-dag} w, |w|^2 -> alpha ; at = A^{-dag} g5 H_eo g5 wt ;
+        // r -= alpha (w - g5 H_oe g5 at / 4), |r|^2 -> beta ; x += alpha p, p = r + beta p
+        cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
         o.iters++;
         o.applies += 2;
         if (o.iters % check_every == 0 || o.iters == maxit) {
@@ -293,9 +318,91 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
     return o;
 }
 
+// ------------------------------------------------------------------ mixed precision CG
+// FP64 normal residual r = Dhat^dag (bh - Dhat x) into W.r; returns |r|^2 (host sync).
+double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const SiteOp* Ai, const SiteOp* Ad) {
+    {
+        auto a = hop_args<double>(ctx, 0);
+        a.in = x; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
+        hop<double>(ctx, false, HM_SITE, false, a);
+    }
+    {
+        auto a = hop_args<double>(ctx, 1);
+        a.in = W.u; a.out = W.w; a.out2 = W.wt; a.aux = x; a.opA = Ai; a.opB = Ad; a.cz = -0.25; a.caux = 1.0;
+        a.red = red_of(ctx, SC_TMP + 10, EPI_STORE);
+        hop<double>(ctx, false, HM_SCHUR_W, true, a);
+    }
+    // rho = bh - Dhat x ; r = Dhat^dag rho
+    HIPCHK(launch_axpby<double>(1.0, W.bh, -1.0, W.w, ctx->nh, nullptr, ctx->st));
+    HIPCHK(launch_site<double>(ctx->Ns, true, W.w, W.wt, Ad, ctx->g.Vh, ctx->st));
+    {
+        auto a = hop_args<double>(ctx, 0);
+        a.in = W.wt; a.out = W.at; a.opA = Ad; a.cz = 1.0; a.caux = 0.0;
+        hop<double>(ctx, true, HM_SITE, false, a);
+    }
+    {
+        auto a = hop_args<double>(ctx, 1);
+        a.in = W.at; a.out = W.r; a.aux = W.w; a.caux = 1.0; a.cz = -0.25;
+        a.red = red_of(ctx, SC_TMP + 11, EPI_STORE);
+        hop<double>(ctx, true, HM_LIN, true, a);
+    }
+    sync_scal(ctx);
+    return ctx->hscal[SC_TMP + 11];
+}
+
+// Reliable-update CG: FP32 storage and arithmetic for the Krylov iteration, FP64 solution
+// accumulation and FP64 residual replacement whenever |r| has dropped by delta since the
+// last replacement.  Solves Dhat W.xcg = W.bh to |r_normal| <= tol_n |r_normal,0|.
+CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
+               double delta, int* updates) {
+    const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+    const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+    const Work32 F = carve32(ctx);
+    const size_t nh = ctx->nh;
+    CgOut o;
+    if (delta <= 0 || delta >= 1) delta = 0.1;
+    if (check_every <= 0) check_every = 1;
+    HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
+    double rr = normal_residual64(ctx, W, W.xcg, Ai, Ad);
+    o.applies = 2;
+    const double rr0 = rr;
+    if (rr0 == 0.0) { o.converged = true; return o; }
+    HIPCHK(launch_convert_d2f(W.r, F.r, nh, ctx->st));
+    HIPCHK(hipMemcpyAsync(F.p, F.r, nh * sizeof(cpx<float>), hipMemcpyDeviceToDevice, ctx->st));
+    HIPCHK(hipMemsetAsync(F.x, 0, nh * sizeof(cpx<float>), ctx->st));
+    while (o.iters < maxit) {
+        // inner FP32 iterations until |r|^2 <= max(delta^2, target) * rr (the last replaced residual)
+        const double tol2 = std::max(delta * delta, tol_n * tol_n * rr0 / rr);
+        HIPCHK(launch_scal_set(ctx->scal, SC_RR, rr, SC_RR0, rr, SC_TOL2, tol2, ctx->st));
+        HIPCHK(launch_scal_set(ctx->scal, SC_DONE, 0.0, -1, 0, -1, 0, ctx->st));
+        int inner = 0;
+        while (o.iters < maxit) {
+            cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
+            o.iters++;
+            inner++;
+            o.applies += 2;
+            if (inner % check_every == 0) {
+                sync_scal(ctx);
+                if (!std::isfinite(ctx->hscal[SC_RR])) { ctx->err = "mixed CG breakdown"; return o; }
+                if (ctx->hscal[SC_DONE] != 0.0) break;
+            }
+        }
+        // reliable update: x_hi += x_lo ; r = Dhat^dag (bh - Dhat x_hi) in FP64
+        HIPCHK(launch_accum_f(W.xcg, F.x, nh, ctx->st));
+        HIPCHK(hipMemsetAsync(F.x, 0, nh * sizeof(cpx<float>), ctx->st));
+        rr = normal_residual64(ctx, W, W.xcg, Ai, Ad);
+        o.applies += 2;
+        if (updates) (*updates)++;
+        if (!std::isfinite(rr)) { ctx->err = "mixed CG: non-finite residual"; return o; }
+        if (rr <= tol_n * tol_n * rr0) { o.converged = true; return o; }
+        HIPCHK(launch_convert_d2f(W.r, F.r, nh, ctx->st));
+    }
+    return o;
+}
+
 // ------------------------------------------------------------------ 5D solve D_T x = c
 struct SolveOut {
-    int iters = 0, applies = 0, restarts = 0;
+    int iters = 0, applies = 0, restarts = 0, updates = 0;
     double relres = 0;
     bool ok = false;
 };
@@ -321,7 +428,8 @@ double norm2_64(eofa_ctx* ctx, const Vec2& v) {
 }
 
 // Even-odd solve of D_T d = rhs (rhs = W.res), result added to W.x.
-CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every) {
+CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
+                   const eofa_solve_params& P, int* updates) {
     const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
     // u_e = A^{-1} res_e ; bh = A^{-1} (res_o + 1/2 H_oe u_e)
     HIPCHK(launch_site<double>(ctx->Ns, false, W.res.h[0], W.u, Ai, ctx->g.Vh, ctx->st));
@@ -330,7 +438,8 @@ CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double 
         a.in = W.u; a.out = W.bh; a.aux = W.res.h[1]; a.caux = 1.0; a.cz = 0.5; a.opA = Ai;
         hop<double>(ctx, false, HM_SITE, false, a);
     }
-    CgOut o = cg64(ctx, W, mp, mm, tol_n, maxit, check_every);
+    CgOut o = (P.prec == EOFA_FP64) ? cg64(ctx, W, mp, mm, tol_n, maxit, check_every)
+                                    : cg_mixed(ctx, W, mp, mm, tol_n, maxit, check_every, P.reliable_delta, updates);
     // d_e = A^{-1} (res_e + 1/2 H_eo d_o) -> u ; x += d
     {
         auto a = hop_args<double>(ctx, 0);
@@ -367,7 +476,7 @@ SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, con
     for (int attempt = 0; attempt < 20; attempt++) {
         // inner target on the normal residual, relative to the current defect
         double tol_n = std::max(0.25 * P.tol / rel, 1e-15);
-        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce);
+        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce, P, &so.updates);
         so.iters += o.iters;
         so.applies += o.applies;
         double r2 = residual64(ctx, W, mp, mm);
@@ -392,7 +501,7 @@ void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
 }
 
 SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
-    REQUIRE(P.prec == EOFA_FP64, EOFA_ENOTIMPL, "only EOFA_FP64 is available in this build");
+    REQUIRE(P.prec == EOFA_FP64 || P.prec == EOFA_MIXED_FP32, EOFA_ENOTIMPL, "EOFA_MIXED_FP16 is not available in this build");
     REQUIRE(P.pc == EOFA_PC_NONE, EOFA_ENOTIMPL, "learned preconditioner not available in this build");
     return solve_dt_fp64(ctx, W, mp, mm, P);
 }
@@ -401,7 +510,7 @@ void fill_info(eofa_solve_info* info, const SolveOut& so, double secs) {
     if (!info) return;
     info->iters = so.iters;
     info->op_applies = so.applies;
-    info->reliable_updates = so.restarts + 1;
+    info->reliable_updates = so.restarts + 1 + so.updates;
     info->fell_back = 0;
     info->true_rel_resid = so.relres;
     info->seconds = secs;
@@ -448,6 +557,138 @@ eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo
     return EOFA_OK;
 }
 
+// nrep launches of the fused hop (A_T^{-1} epilogue) alternating parities on workspace buffers,
+// under schedule sc; returns the average device ms per launch.
+double time_hop(eofa_ctx* ctx, int prec, int nrep, const Sched& sc) {
+    Work64 W = carve64(ctx);
+    const SiteOp* Ai = site_tab(ctx, SK_AINV, 0.01, 0.01);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto run = [&](int n) {
+        for (int i = 0; i < n; i++) {
+            const int par = i & 1;
+            if (prec == EOFA_FP64) {
+                auto a = hop_args<double>(ctx, par);
+                a.sc = sc;
+                a.in = par ? W.u : W.p; a.out = par ? W.p : W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
+                HIPCHK(launch_hop<double>(ctx->Ns, false, HM_SITE, false, a, ctx->st));
+            } else {
+                auto a = hop_args<float>(ctx, par);
+                a.sc = sc;
+                cpx<float>* pf = (cpx<float>*)W.p;
+                cpx<float>* uf = (cpx<float>*)W.u;
+                a.in = par ? uf : pf; a.out = par ? pf : uf; a.opA = Ai; a.cz = 1.0f; a.caux = 0.0f;
+                HIPCHK(launch_hop<float>(ctx->Ns, false, HM_SITE, false, a, ctx->st));
+            }
+        }
+    };
+    run(2);
+    HIPCHK(hipEventRecord(e0, ctx->st));
+    run(nrep);
+    HIPCHK(hipEventRecord(e1, ctx->st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return t / nrep;
+}
+
+void fill_bench_buffers(eofa_ctx* ctx) {
+    Work64 W = carve64(ctx);
+    // finite, non-trivial contents (0x3F3F... is about 4.4e-4 as a double, 0.75 as a float)
+    HIPCHK(hipMemsetAsync(W.p, 0x3F, ctx->nh * sizeof(cd), ctx->st));
+    HIPCHK(hipMemsetAsync(W.u, 0x3F, ctx->nh * sizeof(cd), ctx->st));
+}
+
+std::vector<Sched> sched_candidates(const eofa_ctx* ctx) {
+    std::vector<Sched> c;
+    const Geom& g = ctx->g;
+    const long lanes_line = (long)g.Lxh * g.Ly * ctx->Ns;  // lanes of one (z, t) line
+    const int nyb = (lanes_line % 256 == 0) ? (int)(lanes_line / 256) : 0;
+    for (int x = 0; x < 2; x++) c.push_back(Sched{0, x, 1, 1, 1, nyb > 0 ? nyb : 1});
+    if (nyb == 0) return c;
+    const int opts[] = {1, 2, 4, 8, 16};
+    for (int x = 0; x < 2; x++)
+        for (int ty : opts)
+            for (int tz : opts)
+                for (int tt : opts) {
+                    if (nyb % ty || g.Lz % tz || g.Lt % tt) continue;
+                    const int per = ty * tz * tt;
+                    if (per < 16 || per > 128) continue;
+                    c.push_back(Sched{1, x, ty, tz, tt, nyb});
+                }
+    return c;
+}
+
+template <typename R> struct ApplyBufs {
+    cpx<R>* in[2];
+    cpx<R>* out[2];
+    cpx<R> *u, *w, *wt, *at;
+};
+
+// out = op(in) on canonical 5D fields, in storage/arithmetic type R.
+template <typename R>
+void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out, const ApplyBufs<R>& B) {
+    const int Ns = ctx->Ns;
+    const size_t nh = ctx->nh;
+    for (int par = 0; par < 2; par++) HIPCHK(launch_pack5<R>(in, B.in[par], ctx->g, par, Ns, 0, ctx->st));
+    switch (op) {
+    case EOFA_OP_DW:
+    case EOFA_OP_HOP:
+    case EOFA_OP_DT:
+    case EOFA_OP_DT_DAG:
+    case EOFA_OP_HT: {
+        const bool dag = (op == EOFA_OP_DT_DAG);
+        const SiteOp* M = site_tab(ctx, dag ? SK_M_DAG : SK_M, mp, mm);
+        for (int par = 0; par < 2; par++) {
+            auto a = hop_args<R>(ctx, par);
+            a.in = B.in[1 - par]; a.self = B.in[par]; a.out = B.out[par]; a.opA = M; a.cz = 1; a.caux = 0;
+            int mode = (op == EOFA_OP_DW) ? HM_DW : (op == EOFA_OP_HOP ? HM_LIN : HM_DT);
+            hop<R>(ctx, dag, mode, false, a);
+        }
+        break;
+    }
+    case EOFA_OP_AT_INV: {
+        const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+        for (int par = 0; par < 2; par++) HIPCHK(launch_site<R>(Ns, false, B.in[par], B.out[par], Ai, ctx->g.Vh, ctx->st));
+        break;
+    }
+    default: {  // SCHUR, SCHUR_DAG, SCHUR_NORMAL
+        const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+        const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+        HIPCHK(hipMemsetAsync(B.out[0], 0, nh * sizeof(cpx<R>), ctx->st));
+        const cpx<R>* src = B.in[1];
+        if (op != EOFA_OP_SCHUR_DAG) {
+            auto a = hop_args<R>(ctx, 0);
+            a.in = src; a.out = B.u; a.opA = Ai; a.cz = 1; a.caux = 0;
+            hop<R>(ctx, false, HM_SITE, false, a);
+            auto b = hop_args<R>(ctx, 1);
+            b.in = B.u; b.out = B.w; b.out2 = B.wt; b.aux = src; b.opA = Ai; b.opB = Ad; b.cz = (R)-0.25; b.caux = 1;
+            b.red = red_of(ctx, SC_TMP + 7, EPI_STORE);
+            hop<R>(ctx, false, HM_SCHUR_W, true, b);
+            if (op == EOFA_OP_SCHUR) {
+                HIPCHK(hipMemcpyAsync(B.out[1], B.w, nh * sizeof(cpx<R>), hipMemcpyDeviceToDevice, ctx->st));
+                break;
+            }
+            src = B.w;
+        } else {
+            HIPCHK(launch_site<R>(Ns, true, src, B.wt, Ad, ctx->g.Vh, ctx->st));
+        }
+        auto c = hop_args<R>(ctx, 0);
+        c.in = B.wt; c.out = B.at; c.opA = Ad; c.cz = 1; c.caux = 0;
+        hop<R>(ctx, true, HM_SITE, false, c);
+        auto d = hop_args<R>(ctx, 1);
+        d.in = B.at; d.out = B.out[1]; d.aux = src; d.caux = 1; d.cz = (R)-0.25;
+        hop<R>(ctx, true, HM_LIN, false, d);
+    }
+    }
+    // H_T = gamma_5 R5 D_T reflects in s and flips the lower spins on the way out
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_unpack5<R>(B.out[par], out, ctx->g, par, Ns, op == EOFA_OP_HT ? 1 : 0, ctx->st));
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -486,8 +727,6 @@ eofa_status eofa_create(eofa_ctx** out, const int dims[4], int Ns, double m0, co
         ctx->nh = (size_t)(V / 2) * 12 * Ns;
         const size_t maxblk = (ctx->nh + 255) / 256 + 1024;
         HIPCHK(hipMalloc(&ctx->partials, sizeof(double) * maxblk));
-        HIPCHK(hipMalloc(&ctx->counter, sizeof(unsigned) * 4));
-        HIPCHK(hipMemset(ctx->counter, 0, sizeof(unsigned) * 4));
         HIPCHK(hipMalloc(&ctx->scal, sizeof(double) * (SC_N + 256)));
         HIPCHK(hipMemset(ctx->scal, 0, sizeof(double) * (SC_N + 256)));
         HIPCHK(hipHostMalloc(&ctx->hscal, sizeof(double) * SC_N, hipHostMallocDefault));
@@ -619,74 +858,20 @@ eofa_status eofa_apply(eofa_ctx* ctx, int op, double m_plus, double m_minus, con
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
         REQUIRE(in && out && in != out, EOFA_EINVAL, "bad field pointers");
-        REQUIRE(prec == EOFA_FP64, EOFA_ENOTIMPL, "eofa_apply: only EOFA_FP64 in this build");
-        eofa_solve_params P{1e-10, 1, EOFA_FP64, EOFA_PC_NONE, 0, 0, 0};
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be EOFA_FP64 or EOFA_MIXED_FP32");
+        REQUIRE(op >= EOFA_OP_DW && op <= EOFA_OP_SCHUR_NORMAL, EOFA_EINVAL, "unknown op");
+        eofa_solve_params P{1e-10, 1, prec, EOFA_PC_NONE, 0, 0, 0};
         ensure_ws(ctx, needed_bytes(ctx, &P));
-        Work64 W = carve64(ctx);
-        const int Ns = ctx->Ns;
-        const size_t nh = ctx->nh;
-        for (int par = 0; par < 2; par++) HIPCHK(launch_pack5<double>((const cd*)in, W.x.h[par], ctx->g, par, Ns, 0, ctx->st));
-        Vec2 o = W.res;
-        switch (op) {
-        case EOFA_OP_DW:
-        case EOFA_OP_HOP:
-        case EOFA_OP_DT:
-        case EOFA_OP_DT_DAG:
-        case EOFA_OP_HT: {
-            const bool dag = (op == EOFA_OP_DT_DAG);
-            const SiteOp* M = site_tab(ctx, dag ? SK_M_DAG : SK_M, m_plus, m_minus);
-            for (int par = 0; par < 2; par++) {
-                auto a = hop_args<double>(ctx, par);
-                a.in = W.x.h[1 - par]; a.self = W.x.h[par]; a.out = o.h[par]; a.opA = M; a.cz = 1.0; a.caux = 0.0;
-                int mode = (op == EOFA_OP_DW) ? HM_DW : (op == EOFA_OP_HOP ? HM_LIN : HM_DT);
-                hop<double>(ctx, dag, mode, false, a);
-            }
-            break;
+        if (prec == EOFA_FP64) {
+            Work64 W = carve64(ctx);
+            ApplyBufs<double> B{{W.x.h[0], W.x.h[1]}, {W.res.h[0], W.res.h[1]}, W.u, W.w, W.wt, W.at};
+            apply_op<double>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
+        } else {
+            Work32 F = carve32(ctx);
+            ApplyBufs<float> B{{F.x, F.r}, {F.e0, F.e1}, F.u, F.w, F.wt, F.at};
+            apply_op<float>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
         }
-        case EOFA_OP_AT_INV: {
-            const SiteOp* Ai = site_tab(ctx, SK_AINV, m_plus, m_minus);
-            for (int par = 0; par < 2; par++) HIPCHK(launch_site<double>(Ns, false, W.x.h[par], o.h[par], Ai, ctx->g.Vh, ctx->st));
-            break;
-        }
-        case EOFA_OP_SCHUR:
-        case EOFA_OP_SCHUR_DAG:
-        case EOFA_OP_SCHUR_NORMAL: {
-            const SiteOp* Ai = site_tab(ctx, SK_AINV, m_plus, m_minus);
-            const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, m_plus, m_minus);
-            HIPCHK(hipMemsetAsync(o.h[0], 0, nh * sizeof(cd), ctx->st));
-            const cd* src = W.x.h[1];
-            if (op != EOFA_OP_SCHUR_DAG) {
-                auto a = hop_args<double>(ctx, 0);
-                a.in = src; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
-                hop<double>(ctx, false, HM_SITE, false, a);
-                auto b = hop_args<double>(ctx, 1);
-                b.in = W.u; b.out = W.w; b.out2 = W.wt; b.aux = src; b.opA = Ai; b.opB = Ad; b.cz = -0.25; b.caux = 1.0;
-                b.red = red_of(ctx, SC_TMP + 7, EPI_STORE);
-                hop<double>(ctx, false, HM_SCHUR_W, true, b);
-                if (op == EOFA_OP_SCHUR) {
-                    HIPCHK(hipMemcpyAsync(o.h[1], W.w, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
-                    break;
-                }
-                src = W.w;
-            } else {
-                HIPCHK(launch_site<double>(Ns, true, src, W.wt, Ad, ctx->g.Vh, ctx->st));
-            }
-            auto c = hop_args<double>(ctx, 0);
-            c.in = W.wt; c.out = W.at; c.opA = Ad; c.cz = 1.0; c.caux = 0.0;
-            hop<double>(ctx, true, HM_SITE, false, c);
-            auto d = hop_args<double>(ctx, 1);
-            d.in = W.at; d.out = o.h[1]; d.aux = src; d.caux = 1.0; d.cz = -0.25;
-            hop<double>(ctx, true, HM_LIN, false, d);
-            break;
-        }
-        default:
-            REQUIRE(false, EOFA_EINVAL, "unknown op");
-        }
-        // write back; H_T = gamma_5 R5 D_T reflects in s and flips the lower spins
-        for (int par = 0; par < 2; par++)
-            HIPCHK(launch_unpack5<double>(o.h[par], (cd*)out, ctx->g, par, Ns, op == EOFA_OP_HT ? 1 : 0, ctx->st));
         HIPCHK(hipStreamSynchronize(ctx->st));
-        (void)nh;
         return EOFA_OK;
     });
 }
@@ -712,6 +897,64 @@ eofa_status eofa_hop_timing_reset(eofa_ctx* ctx) {
     });
 }
 
+eofa_status eofa_dslash_bench(eofa_ctx* ctx, int prec, int nrep, double* ms, double* alg_bytes) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+        REQUIRE(nrep > 0 && ms, EOFA_EINVAL, "bad arguments");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
+        eofa_solve_params P{1e-10, 1, (eofa_precision)prec, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        fill_bench_buffers(ctx);
+        *ms = time_hop(ctx, prec, nrep, ctx->sched[prec == EOFA_FP64 ? 0 : 1]);
+        const double rs = (prec == EOFA_FP64) ? 16.0 : 8.0;
+        if (alg_bytes) *alg_bytes = (double)ctx->g.Vh * (2.0 * 12 * ctx->Ns * rs + 8 * 9 * rs);
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[6], double* best_ms, double* base_ms) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
+        if (nrep <= 0) nrep = 4;
+        eofa_solve_params P{1e-10, 1, (eofa_precision)prec, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        fill_bench_buffers(ctx);
+        const int k = prec == EOFA_FP64 ? 0 : 1;
+        std::vector<Sched> cand = sched_candidates(ctx);
+        double best = 1e30, base = 0;
+        Sched bs = cand[0];
+        for (size_t i = 0; i < cand.size(); i++) {
+            double t = time_hop(ctx, prec, nrep, cand[i]);
+            if (i == 0) base = t;
+            if (t < best) { best = t; bs = cand[i]; }
+        }
+        ctx->sched[k] = bs;
+        ctx->tuned_ms[k] = best;
+        if (sched_out) {
+            sched_out[0] = bs.mode; sched_out[1] = bs.xcd; sched_out[2] = bs.ty;
+            sched_out[3] = bs.tz; sched_out[4] = bs.tt; sched_out[5] = bs.nyb;
+        }
+        if (best_ms) *best_ms = best;
+        if (base_ms) *base_ms = base;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[6]) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(sched_in, EOFA_EINVAL, "null schedule");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
+        Sched s{sched_in[0], sched_in[1], sched_in[2], sched_in[3], sched_in[4], sched_in[5]};
+        bool ok = false;
+        for (const Sched& c : sched_candidates(ctx))
+            ok |= (c.mode == s.mode && c.xcd == s.xcd && c.ty == s.ty && c.tz == s.tz && c.tt == s.tt && c.nyb == s.nyb);
+        REQUIRE(ok, EOFA_EINVAL, "schedule not valid for this lattice");
+        ctx->sched[prec == EOFA_FP64 ? 0 : 1] = s;
+        return EOFA_OK;
+    });
+}
+
 eofa_status eofa_set_precond(eofa_ctx* ctx, const void* weights_dev, size_t bytes) {
     return guarded(ctx, [&]() -> eofa_status {
         (void)weights_dev; (void)bytes;
@@ -731,7 +974,6 @@ void eofa_destroy(eofa_ctx* ctx) {
     }
     if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
     if (ctx->partials) (void)hipFree(ctx->partials);
-    if (ctx->counter) (void)hipFree(ctx->counter);
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (auto& e : ctx->ev_pool) {

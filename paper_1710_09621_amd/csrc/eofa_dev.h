@@ -241,13 +241,15 @@ __device__ __forceinline__ double block_sum256(double v, double* lds4) {
     return (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
 }
 
-// Reduction slots and epilogues of the "last block finishes" pattern.
+// Reduction: every block writes its partial sum; a one-block finishing kernel (k_finish)
+// adds the partials in a fixed order and applies an epilogue to the device scalars.  No
+// atomics and no cross-XCD fences inside the producing kernel; the result is bitwise
+// reproducible run to run.
 struct Red {
     double* partials;   // >= gridDim.x doubles
-    unsigned* counter;  // zero before the launch; the finishing block resets it
     double* scal;       // device scalars
     int slot;           // where the sum goes
-    int epi;            // epilogue (see finish_sum)
+    int epi;            // epilogue (see finish_partials)
 };
 
 enum : int {
@@ -258,51 +260,41 @@ enum : int {
     SC_RR0 = 4,     // |r_0|^2 (stop reference)
     SC_DONE = 5,    // 1 when converged (read by graph replays)
     SC_TOL2 = 6,    // stop threshold on |r|^2 / |r_0|^2
-    SC_TMP = 8,     // 8..15 free slots for norms
+    SC_TMP = 8,     // 8..31 free slots for norms
     SC_N = 32
 };
 enum : int { EPI_STORE = 0, EPI_CG_W = 1, EPI_CG_R = 2, EPI_CG_INIT = 3 };
 
 // Called by every thread of every block with the block's sum (same value in all threads).
 __device__ __forceinline__ void finish_sum(const Red& rd, double bsum) {
-    __shared__ int am_last;
+    if (threadIdx.x == 0) rd.partials[blockIdx.x] = bsum;
+}
+
+// Sum partials[0..n) in a fixed order (256 threads) and apply the epilogue.
+__device__ __forceinline__ void finish_partials(const double* partials, unsigned n, double* S, int slot, int epi) {
     __shared__ double lds[4];
-    if (threadIdx.x == 0) {
-        rd.partials[blockIdx.x] = bsum;
-        __threadfence();
-        unsigned prev = atomicAdd(rd.counter, 1u);
-        am_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!am_last) return;
-    __threadfence();
     double s = 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x)
-        s += __hip_atomic_load(rd.partials + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (unsigned i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
     s = block_sum256(s, lds);
     if (threadIdx.x == 0) {
-        double* S = rd.scal;
-        switch (rd.epi) {
-        case EPI_CG_W: {        // s = |Dhat p|^2
+        switch (epi) {
+        case EPI_CG_W:          // s = |Dhat p|^2
             S[SC_WW] = s;
             S[SC_ALPHA] = S[SC_RR] / s;
             break;
-        }
-        case EPI_CG_R: {        // s = |r_new|^2
+        case EPI_CG_R:          // s = |r_new|^2
             S[SC_BETA] = s / S[SC_RR];
             S[SC_RR] = s;
             if (s <= S[SC_TOL2] * S[SC_RR0]) S[SC_DONE] = 1.0;
             break;
-        }
-        case EPI_CG_INIT: {     // s = |r_0|^2
+        case EPI_CG_INIT:       // s = |r_0|^2
             S[SC_RR] = s;
             S[SC_RR0] = s;
             S[SC_DONE] = (s == 0.0) ? 1.0 : 0.0;
             break;
+        default:
+            S[slot] = s;
         }
-        default: S[rd.slot] = s;
-        }
-        *rd.counter = 0u;
     }
 }
 

@@ -8,8 +8,18 @@ namespace eofa {
 
 enum : int { HM_LIN = 0, HM_SITE = 1, HM_SCHUR_W = 2, HM_SCHUR_Q = 3, HM_DT = 4, HM_DW = 5 };
 
+// Order in which workgroups visit the lattice (chosen per lattice by the autotuner).
+// The cb index space of one parity is viewed as [t][z][yb] with yb = workgroup index along
+// the (xh, y) plane line (nyb workgroups per line).  mode 0: linear.  mode 1: 3D tiles of
+// ty x tz x tt workgroups visited tile by tile.  xcd != 0: every XCD (the 8 L2 domains) gets
+// one contiguous range of the visiting sequence instead of every 8th workgroup.
+struct Sched {
+    int mode, xcd, ty, tz, tt, nyb;
+};
+
 template <typename R> struct HopArgs {
     Geom g;
+    Sched sc;
     int par;                  // parity of the output sites
     const cpx<R>* in;         // half field of parity 1 - par (the hop input)
     const cpx<R>* Uown;       // packed links of parity par
@@ -35,6 +45,8 @@ template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>
 template <typename R> hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red,
                                               hipStream_t st);
 template <typename R> hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st);
+// sets S[s_i] = v_i for the slots s_i >= 0 (stream-ordered, no host buffer)
+hipError_t launch_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2, hipStream_t st);
 hipError_t launch_convert_d2f(const cd* in, cpx<float>* out, size_t n, hipStream_t st);
 hipError_t launch_convert_f2d(const cpx<float>* in, cd* out, size_t n, hipStream_t st);
 hipError_t launch_accum_f(cd* xhi, const cpx<float>* xlo, size_t n, hipStream_t st);

@@ -15,10 +15,18 @@ namespace eofa {
 //   HM_SCHUR_Q q = caux*aux + cz*z;  out = aux2 - alpha*q;  sum |out|^2 -> beta  (CG residual update)
 //   HM_DT      out = caux*aux + cz*((4-m0) self + A(self) - z/2)                (D_T, A = M or M^T)
 //   HM_DW      out = caux*aux + cz*((4-m0) self - z/2)                          (D_w on every slice)
+#ifndef HOP_FENCE
+#define HOP_FENCE() __builtin_amdgcn_sched_barrier(0)
+#endif
+#ifndef HOP_LDS_LINKS
+#define HOP_LDS_LINKS 1
+#endif
+
+// One direction mu of the hop: forward (1 - S gamma) U in(x+mu) and backward (1 + S gamma) U^dag in(x-mu).
+// Uf / Ub point at the 9 complex entries of U_mu(x) and U_mu(x-mu) (global memory or LDS).
 template <int NS, bool DAG, int MU, typename R>
-__device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict__ in,
-                                       const cpx<R>* __restrict__ Uown, const cpx<R>* __restrict__ Uoth,
-                                       int cb, const int nb[8], int s) {
+__device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict__ in, const cpx<R>* Uf,
+                                       const cpx<R>* Ub, const int nb[8], int s) {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     {
@@ -28,34 +36,105 @@ __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict_
         for (int j = 0; j < 12; j++) p[j] = src[j * NS];
         cpx<R> h[6], w[6], U[9];
         project<MU, SF>(p, h);
-        const cpx<R>* up = Uown + ((size_t)cb * 4 + MU) * 9;
 #pragma unroll
-        for (int k = 0; k < 9; k++) U[k] = up[k];
+        for (int k = 0; k < 9; k++) U[k] = Uf[k];
         link_mul<false>(U, h, w);
         reconstruct<MU, SF>(acc, w);
     }
     {
-        const int n = nb[2 * MU + 1];
-        const cpx<R>* src = in + (size_t)n * 12 * NS + s;
+        const cpx<R>* src = in + (size_t)nb[2 * MU + 1] * 12 * NS + s;
         cpx<R> p[12];
 #pragma unroll
         for (int j = 0; j < 12; j++) p[j] = src[j * NS];
         cpx<R> h[6], w[6], U[9];
         project<MU, SB>(p, h);
-        const cpx<R>* up = Uoth + ((size_t)n * 4 + MU) * 9;
 #pragma unroll
-        for (int k = 0; k < 9; k++) U[k] = up[k];
+        for (int k = 0; k < 9; k++) U[k] = Ub[k];
         link_mul<true>(U, h, w);
         reconstruct<MU, SB>(acc, w);
     }
 }
 
-#ifndef HOP_FENCE
-#define HOP_FENCE() __builtin_amdgcn_sched_barrier(0)
+#ifndef HOP_PIPE
+#define HOP_PIPE 0
 #endif
-#ifndef HOP_WAVES
-#define HOP_WAVES 2
-#endif
+
+// Neighbour n of the hop (n = 2 mu + 0 forward, 2 mu + 1 backward) on an already loaded spinor p.
+template <bool DAG, int N, typename R>
+__device__ __forceinline__ void hop_term(cpx<R> acc[12], const cpx<R> p[12], const cpx<R>* Ul) {
+    constexpr int MU = N / 2;
+    constexpr bool FWD = (N % 2) == 0;
+    constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);
+    cpx<R> h[6], w[6], U[9];
+    project<MU, S>(p, h);
+#pragma unroll
+    for (int k = 0; k < 9; k++) U[k] = Ul[k];
+    link_mul<!FWD>(U, h, w);
+    reconstruct<MU, S>(acc, w);
+}
+
+template <int NS, typename R>
+__device__ __forceinline__ void load_spinor(cpx<R> p[12], const cpx<R>* __restrict__ in, int n, int s) {
+    const cpx<R>* src = in + (size_t)n * 12 * NS + s;
+#pragma unroll
+    for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+}
+
+// Software-pipelined walk over the 8 neighbours: the spinor of neighbour n+1 is in flight while
+// neighbour n is multiplied.  Link of neighbour n: sU[n/2] (forward) or sU[4 + n/2] (backward).
+template <int NS, bool DAG, int N, typename R>
+__device__ __forceinline__ void hop_pipe(cpx<R> acc[12], cpx<R> cur[12], const cpx<R>* __restrict__ in,
+                                         const cpx<R> (*sU)[9], const int nb[8], int s) {
+    if constexpr (N < 8) {
+        cpx<R> nxt[12];
+        if constexpr (N < 7) load_spinor<NS>(nxt, in, nb[N + 1], s);
+        hop_term<DAG, N>(acc, cur, sU[(N % 2 == 0) ? N / 2 : 4 + N / 2]);
+        if constexpr (N < 7) hop_pipe<NS, DAG, N + 1>(acc, nxt, in, sU, nb, s);
+    }
+}
+
+// z = hop(in) at (cb, s).  With HOP_LDS_LINKS the workgroup first stages the 8 links of each of
+// its 256/NS sites in LDS (each link entry read once from global memory instead of once per slice).
+template <int NS, bool DAG, typename R>
+__device__ __forceinline__ void hop_all(cpx<R> z[12], const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ Uown,
+                                        const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s) {
+#pragma unroll
+    for (int j = 0; j < 12; j++) z[j] = {0, 0};
+    if constexpr (HOP_LDS_LINKS && NS >= 8) {
+        constexpr int SITES = 256 / NS;
+        __shared__ cpx<R> sU[SITES][8][9];
+        const int ls = threadIdx.x / NS;  // local site of this lane
+        for (int e = s; e < 72; e += NS) {
+            const int l = e / 9, k = e % 9;
+            const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k
+                                        : Uoth + ((size_t)nb[2 * (l - 4) + 1] * 4 + (l - 4)) * 9 + k;
+            sU[ls][l][k] = *src;
+        }
+        __syncthreads();
+        if constexpr (HOP_PIPE) {
+            cpx<R> cur[12];
+            load_spinor<NS>(cur, in, nb[0], s);
+            hop_pipe<NS, DAG, 0>(z, cur, in, sU[ls], nb, s);
+            return;
+        }
+        hop_mu<NS, DAG, 0>(z, in, sU[ls][0], sU[ls][4], nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 1>(z, in, sU[ls][1], sU[ls][5], nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 2>(z, in, sU[ls][2], sU[ls][6], nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 3>(z, in, sU[ls][3], sU[ls][7], nb, s);
+    } else {
+        hop_mu<NS, DAG, 0>(z, in, Uown + ((size_t)cb * 4 + 0) * 9, Uoth + ((size_t)nb[1] * 4 + 0) * 9, nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 1>(z, in, Uown + ((size_t)cb * 4 + 1) * 9, Uoth + ((size_t)nb[3] * 4 + 1) * 9, nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 2>(z, in, Uown + ((size_t)cb * 4 + 2) * 9, Uoth + ((size_t)nb[5] * 4 + 2) * 9, nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 3>(z, in, Uown + ((size_t)cb * 4 + 3) * 9, Uoth + ((size_t)nb[7] * 4 + 3) * 9, nb, s);
+    }
+}
+
 // v += c * aux[j * NS] for the 12 components (aux already offset to this lane's element)
 template <int NS, typename R>
 __device__ __forceinline__ void add_aux_ns(cpx<R> v[12], const cpx<R>* __restrict__ aux, R c) {
@@ -68,10 +147,31 @@ __device__ __forceinline__ void add_aux_ns(cpx<R> v[12], const cpx<R>* __restric
 }
 #define add_aux(v, ptr, c) add_aux_ns<NS>(v, ptr, c)
 
+// Workgroup -> tile of 256 lanes, following the schedule (see Sched).
+__device__ __forceinline__ int tile_of(int b, int n, const Sched& sc, const Geom& g) {
+    if (sc.xcd) {  // hardware dispatches workgroup b to XCD b % 8
+        const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+        b = x * q + (x < r ? x : r) + i;
+    }
+    if (sc.mode == 1) {
+        const int per = sc.ty * sc.tz * sc.tt;
+        const int intra = b % per, tile = b / per;
+        const int nyt = sc.nyb / sc.ty, nzt = g.Lz / sc.tz;
+        const int yy = intra % sc.ty, zz = (intra / sc.ty) % sc.tz, tq = intra / (sc.ty * sc.tz);
+        const int ty = tile % nyt, tz = (tile / nyt) % nzt, tt = tile / (nyt * nzt);
+        const int yb = ty * sc.ty + yy, z = tz * sc.tz + zz, t = tt * sc.tt + tq;
+        b = yb + sc.nyb * (z + g.Lz * t);
+    }
+    return b;
+}
+#ifndef HOP_WAVES
+#define HOP_WAVES 2
+#endif
+
 template <int NS, bool DAG, int MODE, bool RED, typename R>
 __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
     if (a.done && *a.done != 0.0) return;
-    const int tid = blockIdx.x * 256 + threadIdx.x;
+    const int tid = tile_of(blockIdx.x, gridDim.x, a.sc, a.g) * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int s = lane & (NS - 1);
     int cb = tid / NS;
@@ -80,15 +180,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
     int nb[8];
     neighbours(a.g, cb, a.par, nb);
     cpx<R> z[12];
-#pragma unroll
-    for (int j = 0; j < 12; j++) z[j] = {0, 0};
-    hop_mu<NS, DAG, 0>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
-    HOP_FENCE();
-    hop_mu<NS, DAG, 1>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
-    HOP_FENCE();
-    hop_mu<NS, DAG, 2>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
-    HOP_FENCE();
-    hop_mu<NS, DAG, 3>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
+    hop_all<NS, DAG>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
 
     const size_t base = (size_t)cb * 12 * NS + s;
     double nrm = 0.0;
@@ -357,12 +449,27 @@ __global__ __launch_bounds__(256) void k_combine(const cd* __restrict__ phi, con
     finish_sum(red, block_sum256(acc, lds));
 }
 
-// 4D canonical field zero/copy helpers are done with hipMemsetAsync / hipMemcpyAsync.
+__global__ void k_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2) {
+    if (threadIdx.x == 0) {
+        if (s0 >= 0) S[s0] = v0;
+        if (s1 >= 0) S[s1] = v1;
+        if (s2 >= 0) S[s2] = v2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partials, unsigned n, double* S, int slot,
+                                                int epi) {
+    finish_partials(partials, n, S, slot, epi);
+}
 
 // ===================================================================== launchers
+static inline void finish(const Red& r, unsigned nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, r.partials, nblocks, r.scal, r.slot, r.epi);
+}
+
 static inline int nblk(size_t n) {
     size_t b = (n + 255) / 256;
-    return (int)(b > 65535 * 8 ? 65535 * 8 : b);
+    return (int)(b > 4096 ? 4096 : b);
 }
 
 #define NS_SWITCH(NSV, ...)                                            \
@@ -392,6 +499,7 @@ hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a,
     NS_SWITCH(Ns, if (dag) { HOP_MODES(true) } else { HOP_MODES(false) });
 #undef HOP_MODES
 #undef HOP_L
+    if (red || mode == HM_SCHUR_W || mode == HM_SCHUR_Q) finish(a.red, (unsigned)grid, st);
     return hipGetLastError();
 }
 template hipError_t launch_hop<double>(int, bool, int, bool, const HopArgs<double>&, hipStream_t);
@@ -417,8 +525,10 @@ template hipError_t launch_cg_xp<float>(cpx<float>*, cpx<float>*, const cpx<floa
 
 template <typename R>
 hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red, hipStream_t st) {
-    if (red) hipLaunchKernelGGL((k_axpby<R, true>), dim3(nblk(n)), dim3(256), 0, st, a, x, b, y, n, *red);
-    else hipLaunchKernelGGL((k_axpby<R, false>), dim3(nblk(n)), dim3(256), 0, st, a, x, b, y, n, Red{});
+    if (red) {
+        hipLaunchKernelGGL((k_axpby<R, true>), dim3(nblk(n)), dim3(256), 0, st, a, x, b, y, n, *red);
+        finish(*red, (unsigned)nblk(n), st);
+    } else hipLaunchKernelGGL((k_axpby<R, false>), dim3(nblk(n)), dim3(256), 0, st, a, x, b, y, n, Red{});
     return hipGetLastError();
 }
 template hipError_t launch_axpby<double>(double, const cd*, double, cd*, size_t, const Red*, hipStream_t);
@@ -427,10 +537,16 @@ template hipError_t launch_axpby<float>(float, const cpx<float>*, float, cpx<flo
 template <typename R>
 hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st) {
     hipLaunchKernelGGL((k_norm2<R>), dim3(nblk(n)), dim3(256), 0, st, x, n, red);
+    finish(red, (unsigned)nblk(n), st);
     return hipGetLastError();
 }
 template hipError_t launch_norm2<double>(const cd*, size_t, const Red&, hipStream_t);
 template hipError_t launch_norm2<float>(const cpx<float>*, size_t, const Red&, hipStream_t);
+
+hipError_t launch_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2, hipStream_t st) {
+    hipLaunchKernelGGL(k_scal_set, dim3(1), dim3(64), 0, st, S, s0, v0, s1, v1, s2, v2);
+    return hipGetLastError();
+}
 
 hipError_t launch_convert_d2f(const cd* in, cpx<float>* out, size_t n, hipStream_t st) {
     hipLaunchKernelGGL((k_convert<double, float>), dim3(nblk(n)), dim3(256), 0, st, in, out, n);
@@ -479,6 +595,7 @@ hipError_t launch_combine(const cd* phi, const cd* xh, cd* out, const Geom& g, i
                           const double* Om, int accumulate, const Red& red, hipStream_t st) {
     hipLaunchKernelGGL(k_combine, dim3(nblk((size_t)g.Vh * 12)), dim3(256), 0, st, phi, xh, out, g, par, Ns, chir, ck,
                        Om, accumulate, red);
+    finish(red, (unsigned)nblk((size_t)g.Vh * 12), st);
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libeofa.so")
+LIB_PATH = os.environ.get("EOFA_LIB") or os.path.join(_HERE, "libeofa.so")
 _lib = None
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
@@ -77,6 +77,9 @@ def load():
         "eofa_hop_timing": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)],
         "eofa_hop_timing_reset": [P],
         "eofa_set_precond": [P, P, Z],
+        "eofa_dslash_bench": [P, I, I, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "eofa_autotune": [P, I, I, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "eofa_set_schedule": [P, I, C.POINTER(C.c_int)],
         "eofa_last_error": [P],
         "eofa_destroy": [P],
     }
@@ -95,7 +98,7 @@ def exported_symbols():
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
                         "eofa_chiral_action", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
-                        "eofa_apply", "eofa_hop_timing", "eofa_hop_timing_reset", "eofa_set_precond",
+                        "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_hop_timing", "eofa_hop_timing_reset", "eofa_set_precond",
                         "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
 
 
@@ -179,7 +182,7 @@ class Context:
     def apply(self, op, x, mp=1.0, mm=1.0, prec=FP64):
         x = self._c128(x, self.shape5)
         out = self.torch.empty_like(x)
-        self._prep_ws(params())
+        self._prep_ws(params(prec=prec))
         self._check(self.lib.eofa_apply(self.h, OPS[op] if isinstance(op, str) else int(op), float(mp), float(mm),
                                         _ptr(x), _ptr(out), int(prec)), f"apply({op})")
         return out
@@ -235,6 +238,52 @@ class Context:
         st = self.lib.eofa_chiral_action_batch(self.h, n, chir, m3, m4, mo, pin, pout, S, C.byref(p), info)
         self._check(st, "chiral_action_batch")
         return [Result(outs[j], S[j], [info[j].as_dict()]) for j in range(n)]
+
+    def dslash_bench(self, nrep=20, prec=FP64):
+        ms, b = C.c_double(), C.c_double()
+        self._prep_ws(params(prec=prec))
+        self._check(self.lib.eofa_dslash_bench(self.h, int(prec), int(nrep), C.byref(ms), C.byref(b)), "dslash_bench")
+        return dict(ms=ms.value, bytes=b.value, gbs=b.value / (ms.value * 1e-3) / 1e9)
+
+    def autotune(self, prec=FP64, nrep=4, cache=None):
+        """Pick the hop schedule for this lattice; cache: JSON path keyed by (dims, Ns, prec, arch)."""
+        import json
+        key = f"{'x'.join(map(str, self.dims))}_Ns{self.Ns}_p{int(prec)}_{self._arch()}"
+        sched = (C.c_int * 6)()
+        self._prep_ws(params(prec=prec))
+        if cache and os.path.exists(cache):
+            try:
+                with open(cache) as f:
+                    entry = json.load(f).get(key)
+                if entry:
+                    sched[:] = entry["sched"]
+                    if self.lib.eofa_set_schedule(self.h, int(prec), sched) == OK:
+                        return dict(entry, cached=True)
+            except (OSError, ValueError):
+                pass
+        best, base = C.c_double(), C.c_double()
+        self._check(self.lib.eofa_autotune(self.h, int(prec), int(nrep), sched, C.byref(best), C.byref(base)),
+                    "autotune")
+        entry = dict(sched=list(sched), best_ms=best.value, base_ms=base.value)
+        if cache:
+            try:
+                data = {}
+                if os.path.exists(cache):
+                    with open(cache) as f:
+                        data = json.load(f)
+                data[key] = entry
+                os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+                with open(cache, "w") as f:
+                    json.dump(data, f, indent=1, sort_keys=True)
+            except (OSError, ValueError):
+                pass
+        return dict(entry, cached=False)
+
+    def _arch(self):
+        try:
+            return self.torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
+        except Exception:
+            return "gfx"
 
     def hop_timing(self, enable=True):
         ms, n, b = C.c_double(), C.c_long(), C.c_double()

@@ -1,0 +1,50 @@
+"""Profiling driver for the fused even-odd hop (run it under rocprofv3).
+
+    python -m paper_1710_09621_amd.profile_hop [--dims 32 32 32 64] [--Ns 16] [--nrep 10]
+
+Sets up the seeded lattice, autotunes the hop schedule, launches the FP64 hop nrep times
+(the kernel behind the bench's dslash figure) and then applies the site-local A_T^{-1}
+(k_site: one streaming read and one streaming write of a half field per parity, the same
+access pattern as the hop's spinor traffic) once, so that hardware byte counters can be
+calibrated against a kernel of known traffic in the same process.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dims", type=int, nargs=4, default=[32, 32, 32, 64])
+    ap.add_argument("--Ns", type=int, default=16)
+    ap.add_argument("--eps", type=float, default=0.7)
+    ap.add_argument("--nrep", type=int, default=10)
+    ap.add_argument("--prec", type=int, default=0)
+    args = ap.parse_args()
+    import numpy as np
+    import torch
+    from paper_1710_09621_amd import eofa as E
+    from paper_1710_09621_amd import inputs as IN
+    dims = tuple(args.dims)
+    U = IN.gauge_links(dims, args.eps, 5)
+    ctx = E.Context(dims, args.Ns, IN.M0, IN.optimal_omega(args.Ns))
+    ctx.set_gauge(U)
+    tune = ctx.autotune(prec=args.prec)
+    r = ctx.dslash_bench(nrep=args.nrep, prec=args.prec)
+    x = torch.randn(ctx.shape5, dtype=torch.complex128, device="cuda")
+    ctx.apply("AT_INV", x, 0.01, 0.01)
+    torch.cuda.synchronize()
+    Vh = int(np.prod(dims)) // 2
+    print(json.dumps(dict(dims=dims, Ns=args.Ns, prec=args.prec, schedule=tune["sched"], ms=r["ms"], gbs=r["gbs"],
+                          alg_bytes=r["bytes"], site_kernel_bytes_each_way=Vh * 12 * args.Ns * 16)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
