@@ -170,13 +170,13 @@ eofa_status eofa_dslash_bench(eofa_ctx *ctx, int prec, int nrep, double *ms, dou
  * Autotuner of the hop kernels' workgroup schedule (XCD-contiguous ranges, 3D tiling of the
  * workgroup grid) for this lattice and storage precision: times every candidate with
  * nrep launches of the fused hop (0: 4) and keeps the fastest for all later solves.
- * sched_out[6] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb} for a persistent cache;
+ * sched_out[7] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb, ord} for a persistent cache;
  * *best_ms / *base_ms (may be NULL) the chosen and the linear-order launch times.
  */
-eofa_status eofa_autotune(eofa_ctx *ctx, int prec, int nrep, int sched_out[6], double *best_ms,
+eofa_status eofa_autotune(eofa_ctx *ctx, int prec, int nrep, int sched_out[7], double *best_ms,
                           double *base_ms);
 /* Re-install a schedule returned by eofa_autotune (EINVAL if it does not fit this lattice). */
-eofa_status eofa_set_schedule(eofa_ctx *ctx, int prec, const int sched_in[6]);
+eofa_status eofa_set_schedule(eofa_ctx *ctx, int prec, const int sched_in[7]);
 
 /* Learned preconditioner weights: the packed BF16 blob produced by eofa_cnn_* (see below). */
 eofa_status eofa_set_precond(eofa_ctx *ctx, const void *weights_dev, size_t bytes);

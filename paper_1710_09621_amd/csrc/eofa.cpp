@@ -42,8 +42,11 @@ struct eofa_ctx {
     size_t ws_bytes = 0;
     bool ws_owned = false;
     double* partials = nullptr;
-    double* scal = nullptr;
-    double* hscal = nullptr;  // pinned
+    double* scal = nullptr;   // [0, SC_N): single-system scalars; [SC_N, SC_N+128): coefficient vectors;
+                              // [BATCH_OFF, BATCH_OFF + NRMAX*SC_N): multi-RHS scalars
+    double* hscal = nullptr;  // pinned mirror of scal
+    double* partials_mr = nullptr;
+    int pstride = 0;
     std::map<std::tuple<int, double, double>, SiteOp*> tabs;
     std::string err;
     // hop timing
@@ -54,11 +57,14 @@ struct eofa_ctx {
     long hop_launches = 0;
     double hop_bytes = 0;
     // workgroup schedules of the hop kernels, per storage precision (0: FP64, 1: FP32); set by the autotuner
-    Sched sched[2] = {{0, 0, 1, 1, 1, 1}, {0, 0, 1, 1, 1, 1}};
+    Sched sched[2] = {{0, 0, 1, 1, 1, 1, 0}, {0, 0, 1, 1, 1, 1, 0}};
     double tuned_ms[2] = {0, 0};
 };
 
 namespace {
+
+constexpr int BATCH_OFF = 256;
+constexpr int SCAL_TOTAL = BATCH_OFF + NRMAX * SC_N;
 
 struct Fail {
     eofa_status st;
@@ -133,9 +139,16 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 size_t work64_bytes(const eofa_ctx* ctx) { return 14 * align_up(ctx->nh * sizeof(cd)); }
 size_t work32_bytes(const eofa_ctx* ctx) { return 9 * align_up(ctx->nh * sizeof(cpx<float>)); }
 
-size_t needed_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
+// per system of a multi-RHS batch: FP64 solution accumulator and Schur source, 7 Krylov vectors
+size_t batch_sys_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
+    const size_t kr = (p && p->prec != EOFA_FP64) ? sizeof(cpx<float>) : sizeof(cd);
+    return 2 * align_up(ctx->nh * sizeof(cd)) + 7 * align_up(ctx->nh * kr);
+}
+
+size_t needed_bytes(const eofa_ctx* ctx, const eofa_solve_params* p, int nrhs = 1) {
     size_t b = work64_bytes(ctx);
     if (p && p->prec != EOFA_FP64) b += work32_bytes(ctx);
+    if (nrhs > 1 && ctx->Ns >= 8) b += (size_t)std::min(nrhs, NRMAX) * batch_sys_bytes(ctx, p);
     return b;
 }
 
@@ -320,7 +333,8 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
 
 // ------------------------------------------------------------------ mixed precision CG
 // FP64 normal residual r = Dhat^dag (bh - Dhat x) into W.r; returns |r|^2 (host sync).
-double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const SiteOp* Ai, const SiteOp* Ad) {
+double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const cd* bh, const SiteOp* Ai,
+                         const SiteOp* Ad) {
     {
         auto a = hop_args<double>(ctx, 0);
         a.in = x; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
@@ -333,7 +347,7 @@ double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const Site
         hop<double>(ctx, false, HM_SCHUR_W, true, a);
     }
     // rho = bh - Dhat x ; r = Dhat^dag rho
-    HIPCHK(launch_axpby<double>(1.0, W.bh, -1.0, W.w, ctx->nh, nullptr, ctx->st));
+    HIPCHK(launch_axpby<double>(1.0, bh, -1.0, W.w, ctx->nh, nullptr, ctx->st));
     HIPCHK(launch_site<double>(ctx->Ns, true, W.w, W.wt, Ad, ctx->g.Vh, ctx->st));
     {
         auto a = hop_args<double>(ctx, 0);
@@ -363,7 +377,7 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
     if (delta <= 0 || delta >= 1) delta = 0.1;
     if (check_every <= 0) check_every = 1;
     HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
-    double rr = normal_residual64(ctx, W, W.xcg, Ai, Ad);
+    double rr = normal_residual64(ctx, W, W.xcg, W.bh, Ai, Ad);
     o.applies = 2;
     const double rr0 = rr;
     if (rr0 == 0.0) { o.converged = true; return o; }
@@ -390,7 +404,7 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
         // reliable update: x_hi += x_lo ; r = Dhat^dag (bh - Dhat x_hi) in FP64
         HIPCHK(launch_accum_f(W.xcg, F.x, nh, ctx->st));
         HIPCHK(hipMemsetAsync(F.x, 0, nh * sizeof(cpx<float>), ctx->st));
-        rr = normal_residual64(ctx, W, W.xcg, Ai, Ad);
+        rr = normal_residual64(ctx, W, W.xcg, W.bh, Ai, Ad);
         o.applies += 2;
         if (updates) (*updates)++;
         if (!std::isfinite(rr)) { ctx->err = "mixed CG: non-finite residual"; return o; }
@@ -463,17 +477,16 @@ int auto_check_every(const eofa_ctx* ctx, const eofa_solve_params& P) {
     return 16;
 }
 
-SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
-    SolveOut so;
-    const double cn2 = norm2_64(ctx, W.c);
-    for (int par = 0; par < 2; par++) {
-        HIPCHK(hipMemsetAsync(W.x.h[par], 0, ctx->nh * sizeof(cd), ctx->st));
-        HIPCHK(hipMemcpyAsync(W.res.h[par], W.c.h[par], ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
-    }
-    if (cn2 == 0.0) { so.ok = true; return so; }
-    double rel = 1.0;
+// Defect correction on D_T x = c with W.x holding the current solution and W.res = c - D_T x:
+// even-odd Krylov solves of the defect until ||c - D_T x|| / ||c|| <= tol.
+void refine(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P, double cn2, double rel,
+            SolveOut& so) {
     const int ce = auto_check_every(ctx, P);
+    so.relres = rel;
     for (int attempt = 0; attempt < 20; attempt++) {
+        if (rel <= P.tol) { so.ok = true; return; }
+        if (so.iters >= P.max_iter) return;
+        if (attempt > 0) so.restarts++;
         // inner target on the normal residual, relative to the current defect
         double tol_n = std::max(0.25 * P.tol / rel, 1e-15);
         CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce, P, &so.updates);
@@ -482,12 +495,180 @@ SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, con
         double r2 = residual64(ctx, W, mp, mm);
         rel = std::sqrt(r2 / cn2);
         so.relres = rel;
-        if (!std::isfinite(rel)) { ctx->err = "non-finite residual"; return so; }
-        if (rel <= P.tol) { so.ok = true; return so; }
-        if (so.iters >= P.max_iter) return so;
-        so.restarts++;
+        if (!std::isfinite(rel)) { ctx->err = "non-finite residual"; return; }
     }
+}
+
+SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
+    SolveOut so;
+    const double cn2 = norm2_64(ctx, W.c);
+    for (int par = 0; par < 2; par++) {
+        HIPCHK(hipMemsetAsync(W.x.h[par], 0, ctx->nh * sizeof(cd), ctx->st));
+        HIPCHK(hipMemcpyAsync(W.res.h[par], W.c.h[par], ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    }
+    if (cn2 == 0.0) { so.ok = true; return so; }
+    refine(ctx, W, mp, mm, P, cn2, 1.0, so);
     return so;
+}
+
+// ------------------------------------------------------------------ multi-RHS batch
+struct Sys {
+    double mp = 0, mm = 0;
+    const SiteOp* Ai = nullptr;
+    const SiteOp* Ad = nullptr;
+    cd* xhi = nullptr;  // FP64 solution accumulator (odd sites)
+    cd* bh = nullptr;   // FP64 Schur right-hand side
+    void *x, *r, *p, *u, *w, *wt, *at;  // Krylov vectors in the batch precision
+    double rr0 = 0;
+    bool conv = false;
+    int iters = 0, updates = 0;
+};
+
+void carve_batch(eofa_ctx* ctx, const eofa_solve_params& P, std::vector<Sys>& sys) {
+    char* q = ctx->ws + work64_bytes(ctx) + (P.prec != EOFA_FP64 ? work32_bytes(ctx) : 0);
+    const size_t h64 = align_up(ctx->nh * sizeof(cd));
+    const size_t hk = align_up(ctx->nh * (P.prec != EOFA_FP64 ? sizeof(cpx<float>) : sizeof(cd)));
+    for (Sys& y : sys) {
+        y.xhi = (cd*)q; q += h64;
+        y.bh = (cd*)q; q += h64;
+        void** v[7] = {&y.x, &y.r, &y.p, &y.u, &y.w, &y.wt, &y.at};
+        for (void** pp : v) { *pp = q; q += hk; }
+    }
+}
+
+void ensure_partials_mr(eofa_ctx* ctx) {
+    const int need = (int)(((size_t)ctx->g.Vh * ctx->Ns + 255) / 256) + 1;
+    if (ctx->partials_mr && ctx->pstride >= need) return;
+    if (ctx->partials_mr) HIPCHK(hipFree(ctx->partials_mr));
+    HIPCHK(hipMalloc(&ctx->partials_mr, sizeof(double) * (size_t)need * NRMAX));
+    ctx->pstride = need;
+}
+
+double* sys_scal(eofa_ctx* ctx, int r) { return ctx->scal + BATCH_OFF + r * SC_N; }
+
+void sync_scal_batch(eofa_ctx* ctx, int nr) {
+    HIPCHK(hipMemcpyAsync(ctx->hscal + BATCH_OFF, ctx->scal + BATCH_OFF, sizeof(double) * SC_N * nr,
+                          hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+}
+
+template <typename R> HopArgsMR<R> mr_args(eofa_ctx* ctx, int par, int nr) {
+    HopArgsMR<R> a{};
+    HopArgs<R> b = hop_args<R>(ctx, par);
+    a.g = b.g; a.sc = b.sc; a.par = par; a.nr = nr; a.Uown = b.Uown; a.Uoth = b.Uoth;
+    a.scal = ctx->scal + BATCH_OFF;
+    a.partials = ctx->partials_mr;
+    a.pstride = ctx->pstride;
+    return a;
+}
+
+// One batched CG iteration over the systems (converged ones are skipped on the device).
+template <typename R> void cg_iteration_mr(eofa_ctx* ctx, std::vector<Sys>& sys) {
+    const int nr = (int)sys.size();
+    auto V = [](void* p) { return (cpx<R>*)p; };
+    {
+        auto a = mr_args<R>(ctx, 0, nr);
+        for (int r = 0; r < nr; r++) { a.in[r] = V(sys[r].p); a.out[r] = V(sys[r].u); a.opA[r] = sys[r].Ai; }
+        a.cz = 1; a.caux = 0;
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SITE, a, ctx->st));
+    }
+    {
+        auto a = mr_args<R>(ctx, 1, nr);
+        for (int r = 0; r < nr; r++) {
+            a.in[r] = V(sys[r].u); a.out[r] = V(sys[r].w); a.out2[r] = V(sys[r].wt); a.aux[r] = V(sys[r].p);
+            a.opA[r] = sys[r].Ai; a.opB[r] = sys[r].Ad;
+        }
+        a.cz = (R)-0.25; a.caux = 1; a.epi = EPI_CG_W;
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SCHUR_W, a, ctx->st));
+    }
+    {
+        auto a = mr_args<R>(ctx, 0, nr);
+        for (int r = 0; r < nr; r++) { a.in[r] = V(sys[r].wt); a.out[r] = V(sys[r].at); a.opA[r] = sys[r].Ad; }
+        a.cz = 1; a.caux = 0;
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SITE, a, ctx->st));
+    }
+    {
+        auto a = mr_args<R>(ctx, 1, nr);
+        for (int r = 0; r < nr; r++) {
+            a.in[r] = V(sys[r].at); a.out[r] = V(sys[r].r); a.aux[r] = V(sys[r].w); a.aux2[r] = V(sys[r].r);
+        }
+        a.cz = (R)-0.25; a.caux = 1; a.epi = EPI_CG_R;
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SCHUR_Q, a, ctx->st));
+    }
+    cpx<R>* xs[NRMAX];
+    cpx<R>* ps[NRMAX];
+    cpx<R>* rs[NRMAX];
+    for (int r = 0; r < nr; r++) { xs[r] = V(sys[r].x); ps[r] = V(sys[r].p); rs[r] = V(sys[r].r); }
+    HIPCHK(launch_cg_xp_mr<R>(nr, xs, ps, rs, ctx->scal + BATCH_OFF, ctx->nh, ctx->st));
+}
+
+// Batched CG on the systems' Schur normal equations to |r_normal| <= tol_n |r_normal,0| each.  With R = float
+// every system gets FP64 reliable updates (residual replacement) on its own schedule.
+template <typename R>
+void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_n, int maxit, int ce, double delta) {
+    const int nr = (int)sys.size();
+    const bool mixed = sizeof(R) == 4;
+    if (delta <= 0 || delta >= 1) delta = 0.1;
+    if (ce <= 0) ce = 1;
+    const size_t nb = ctx->nh * sizeof(cpx<R>);
+    auto arm = [&](int r, double rr, double rr_ref) {
+        const double tol2 = mixed ? std::max(delta * delta, tol_n * tol_n * sys[r].rr0 / rr) : tol_n * tol_n;
+        double* S = sys_scal(ctx, r);
+        HIPCHK(launch_scal_set(S, SC_RR, rr, SC_RR0, rr_ref, SC_TOL2, tol2, ctx->st));
+        HIPCHK(launch_scal_set(S, SC_DONE, 0.0, SC_DONEX, 0.0, -1, 0, ctx->st));
+    };
+    for (int r = 0; r < nr; r++) {
+        Sys& y = sys[r];
+        HIPCHK(hipMemsetAsync(y.xhi, 0, ctx->nh * sizeof(cd), ctx->st));
+        HIPCHK(hipMemsetAsync(y.x, 0, nb, ctx->st));
+        double rr = normal_residual64(ctx, W, y.xhi, y.bh, y.Ai, y.Ad);   // r = Dhat^dag bh in W.r
+        y.rr0 = rr;
+        if (rr == 0.0) {
+            y.conv = true;
+            HIPCHK(launch_scal_set(sys_scal(ctx, r), SC_DONE, 1.0, SC_DONEX, 1.0, -1, 0, ctx->st));
+            continue;
+        }
+        if (mixed) HIPCHK(launch_convert_d2f(W.r, (cpx<float>*)y.r, ctx->nh, ctx->st));
+        else HIPCHK(hipMemcpyAsync(y.r, W.r, nb, hipMemcpyDeviceToDevice, ctx->st));
+        HIPCHK(hipMemcpyAsync(y.p, y.r, nb, hipMemcpyDeviceToDevice, ctx->st));
+        arm(r, rr, rr);
+    }
+    int it = 0;
+    while (it < maxit) {
+        bool all = true;
+        for (const Sys& y : sys) all &= y.conv;
+        if (all) break;
+        cg_iteration_mr<R>(ctx, sys);
+        it++;
+        for (Sys& y : sys) if (!y.conv) y.iters++;
+        if (it % ce && it < maxit) continue;
+        sync_scal_batch(ctx, nr);
+        for (int r = 0; r < nr; r++) {
+            Sys& y = sys[r];
+            const double* hs = ctx->hscal + BATCH_OFF + r * SC_N;
+            if (y.conv || hs[SC_DONE] == 0.0) continue;
+            if (!std::isfinite(hs[SC_RR])) { ctx->err = "batched CG breakdown"; y.conv = true; continue; }
+            if (!mixed) { y.conv = true; HIPCHK(hipMemcpyAsync(y.xhi, y.x, nb, hipMemcpyDeviceToDevice, ctx->st)); continue; }
+            // reliable update of system r
+            HIPCHK(launch_accum_f(y.xhi, (const cpx<float>*)y.x, ctx->nh, ctx->st));
+            HIPCHK(hipMemsetAsync(y.x, 0, nb, ctx->st));
+            double rr = normal_residual64(ctx, W, y.xhi, y.bh, y.Ai, y.Ad);
+            y.updates++;
+            if (rr <= tol_n * tol_n * y.rr0 || !std::isfinite(rr)) {
+                y.conv = true;
+                HIPCHK(launch_scal_set(sys_scal(ctx, r), SC_DONE, 1.0, SC_DONEX, 1.0, -1, 0, ctx->st));
+                continue;
+            }
+            HIPCHK(launch_convert_d2f(W.r, (cpx<float>*)y.r, ctx->nh, ctx->st));
+            arm(r, rr, rr);
+        }
+    }
+    if (!mixed)  // systems stopped by max_iter: keep their last iterate
+        for (Sys& y : sys)
+            if (!y.conv) HIPCHK(hipMemcpyAsync(y.xhi, y.x, nb, hipMemcpyDeviceToDevice, ctx->st));
+    if (mixed)
+        for (Sys& y : sys)
+            if (!y.conv) HIPCHK(launch_accum_f(y.xhi, (const cpx<float>*)y.x, ctx->nh, ctx->st));
 }
 
 void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
@@ -518,35 +699,73 @@ void fill_info(eofa_solve_info* info, const SolveOut& so, double secs) {
 
 double kfac(double mj, double mi) { return 2.0 * (mj - mi) / ((1.0 + mj) * (1.0 + mi)); }
 
-// One chiral action; writes (accumulate = 0) or adds (accumulate = 1) its P_chir part into out.
-eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, void* out,
-                        int accumulate, double* S, const eofa_solve_params* P, eofa_solve_info* info) {
-    check_params(ctx, P);
+// Om_s = (-1)^s omega_s^{-1/2} (s = 1..Ns), the vector of Eq.(delta_ij) for this operator.
+std::vector<double> omega_vec(const eofa_ctx* ctx) {
+    std::vector<double> Om(ctx->Ns);
+    for (int s = 0; s < ctx->Ns; s++) Om[s] = ((s % 2 == 0) ? -1.0 : 1.0) / std::sqrt(ctx->omega[s]);
+    return Om;
+}
+
+// W.c = R5 gamma_5 (Om (x) P_chir phi), i.e. c_s = chir Om_{Ns+1-s} P_chir phi, on both parities.
+void make_source(eofa_ctx* ctx, const Work64& W, int chir, const void* phi) {
+    const int Ns = ctx->Ns;
+    std::vector<double> Om = omega_vec(ctx), coef(Ns);
+    for (int s = 0; s < Ns; s++) coef[s] = chir * Om[Ns - 1 - s];
+    double* dcoef = ctx->scal + SC_N;
+    HIPCHK(launch_set_vec(dcoef, Ns, coef.data(), ctx->st));
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_source((const cd*)phi, W.c.h[par], ctx->g, par, Ns, chir, dcoef, ctx->st));
+}
+
+// bh = A^{-1} (c_o + H_oe A^{-1} c_e / 2), the Schur right-hand side of D_T x = c.
+void prep_schur(eofa_ctx* ctx, const Work64& W, const SiteOp* Ai, cd* bh) {
+    HIPCHK(launch_site<double>(ctx->Ns, false, W.c.h[0], W.u, Ai, ctx->g.Vh, ctx->st));
+    auto a = hop_args<double>(ctx, 1);
+    a.in = W.u; a.out = bh; a.aux = W.c.h[1]; a.caux = 1.0; a.cz = 0.5; a.opA = Ai;
+    hop<double>(ctx, false, HM_SITE, false, a);
+}
+
+// W.x = (A^{-1} (c_e + H_eo xo / 2), xo)
+void reconstruct(eofa_ctx* ctx, const Work64& W, const SiteOp* Ai, const cd* xo) {
+    auto a = hop_args<double>(ctx, 0);
+    a.in = xo; a.out = W.x.h[0]; a.aux = W.c.h[0]; a.caux = 1.0; a.cz = 0.5; a.opA = Ai;
+    hop<double>(ctx, false, HM_SITE, false, a);
+    HIPCHK(hipMemcpyAsync(W.x.h[1], xo, ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+}
+
+// out = P_chir phi + chir k Om^T P_chir x (written, or added with accumulate); returns Re phi^dag (this part).
+double combine(eofa_ctx* ctx, const Work64& W, int chir, double k, const void* phi, void* out, int accumulate) {
+    std::vector<double> Om = omega_vec(ctx);
+    double* dOm = ctx->scal + SC_N + 64;
+    HIPCHK(launch_set_vec(dOm, ctx->Ns, Om.data(), ctx->st));
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_combine((const cd*)phi, W.x.h[par], (cd*)out, ctx->g, par, ctx->Ns, chir, chir * k, dOm, accumulate,
+                              red_of(ctx, SC_TMP + 4 + par, EPI_STORE), ctx->st));
+    sync_scal(ctx);
+    return ctx->hscal[SC_TMP + 4] + ctx->hscal[SC_TMP + 5];
+}
+
+double action_k(int chir, double m3, double m4, double mo) { return (chir < 0) ? kfac(mo, m4) : kfac(mo, m3); }
+
+void check_action(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, const void* out) {
     REQUIRE(chir == 1 || chir == -1, EOFA_EINVAL, "chir must be +1 or -1");
     REQUIRE(phi && out, EOFA_EINVAL, "null field pointer");
     REQUIRE(phi != out, EOFA_EINVAL, "phi and out may not alias");
     for (double m : {m3, m4, mo}) REQUIRE(m > 0 && m <= 1, EOFA_EINVAL, "masses must lie in (0, 1]");
+}
+
+// One chiral action; writes (accumulate = 0) or adds (accumulate = 1) its P_chir part into out.
+eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, void* out,
+                        int accumulate, double* S, const eofa_solve_params* P, eofa_solve_info* info) {
+    check_params(ctx, P);
+    check_action(ctx, chir, m3, m4, mo, phi, out);
     auto t0 = std::chrono::steady_clock::now();
     ensure_ws(ctx, needed_bytes(ctx, P));
     Work64 W = carve64(ctx);
-    const int Ns = ctx->Ns;
-    std::vector<double> Om(Ns), coef(Ns);
-    for (int s = 0; s < Ns; s++) Om[s] = ((s % 2 == 0) ? -1.0 : 1.0) / std::sqrt(ctx->omega[s]);  // (-1)^{s+1}, s 1-based
-    for (int s = 0; s < Ns; s++) coef[s] = chir * Om[Ns - 1 - s];
-    const double k = (chir < 0) ? kfac(mo, m4) : kfac(mo, m3);
-    // coefficient vectors travel in the scalar area (slots 16..16+2*Ns within a separate buffer)
-    double* dcoef = ctx->scal + SC_N;
-    double* dOm = dcoef + 64;
-    HIPCHK(hipMemcpyAsync(dcoef, coef.data(), sizeof(double) * Ns, hipMemcpyHostToDevice, ctx->st));
-    HIPCHK(hipMemcpyAsync(dOm, Om.data(), sizeof(double) * Ns, hipMemcpyHostToDevice, ctx->st));
-    for (int par = 0; par < 2; par++)
-        HIPCHK(launch_source((const cd*)phi, W.c.h[par], ctx->g, par, Ns, chir, dcoef, ctx->st));
+    make_source(ctx, W, chir, phi);
     SolveOut so = solve_dt(ctx, W, m3, m4, *P);
-    for (int par = 0; par < 2; par++)
-        HIPCHK(launch_combine((const cd*)phi, W.x.h[par], (cd*)out, ctx->g, par, Ns, chir, chir * k, dOm, accumulate,
-                              red_of(ctx, SC_TMP + 4 + par, EPI_STORE), ctx->st));
-    sync_scal(ctx);  // also completes the host->device copies of the pageable vectors above
-    if (S) *S = ctx->hscal[SC_TMP + 4] + ctx->hscal[SC_TMP + 5];
+    const double s = combine(ctx, W, chir, action_k(chir, m3, m4, mo), phi, out, accumulate);
+    if (S) *S = s;
     collect_timing(ctx);
     double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_info(info, so, secs);
@@ -555,6 +774,75 @@ eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo
         return EOFA_ENOCONV;
     }
     return EOFA_OK;
+}
+
+// n chiral actions through the multi-RHS path, in groups of up to NRMAX systems.
+eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const double* m3, const double* m4,
+                              const double* mo, const void* const* phi, void* const* out, const int* accumulate,
+                              double* S, const eofa_solve_params* P, eofa_solve_info* info) {
+    check_params(ctx, P);
+    for (int j = 0; j < n; j++) check_action(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j]);
+    if (n <= 1 || ctx->Ns < 8 || P->pc != EOFA_PC_NONE) {
+        eofa_status worst = EOFA_OK;
+        for (int j = 0; j < n; j++) {
+            double sj = 0;
+            eofa_status a = chiral_impl(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j], accumulate ? accumulate[j] : 0,
+                                        &sj, P, info ? &info[j] : nullptr);
+            if (S) S[j] = sj;
+            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+            if (a != EOFA_OK) worst = a;
+        }
+        return worst;
+    }
+    ensure_ws(ctx, needed_bytes(ctx, P, n));
+    ensure_partials_mr(ctx);
+    Work64 W = carve64(ctx);
+    eofa_status worst = EOFA_OK;
+    for (int g0 = 0; g0 < n; g0 += NRMAX) {
+        const int nr = std::min(NRMAX, n - g0);
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<Sys> sys(nr);
+        carve_batch(ctx, *P, sys);
+        for (int r = 0; r < nr; r++) {
+            const int j = g0 + r;
+            Sys& y = sys[r];
+            y.mp = m3[j];
+            y.mm = m4[j];
+            y.Ai = site_tab(ctx, SK_AINV, y.mp, y.mm);
+            y.Ad = site_tab(ctx, SK_AINV_DAG, y.mp, y.mm);
+            make_source(ctx, W, chir[j], phi[j]);
+            prep_schur(ctx, W, y.Ai, y.bh);
+        }
+        const double tol_n = 0.25 * P->tol;
+        const int ce = auto_check_every(ctx, *P);
+        if (P->prec == EOFA_FP64) cg_batch<double>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta);
+        else cg_batch<float>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta);
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        const double tb = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / nr;
+        for (int r = 0; r < nr; r++) {
+            const int j = g0 + r;
+            Sys& y = sys[r];
+            auto t1 = std::chrono::steady_clock::now();
+            make_source(ctx, W, chir[j], phi[j]);
+            const double cn2 = norm2_64(ctx, W.c);
+            reconstruct(ctx, W, y.Ai, y.xhi);
+            SolveOut so;
+            so.iters = y.iters;
+            so.updates = y.updates;
+            so.applies = 2 * y.iters + 2 * y.updates + 2;
+            const double rel = cn2 > 0 ? std::sqrt(residual64(ctx, W, y.mp, y.mm) / cn2) : 0.0;
+            refine(ctx, W, y.mp, y.mm, *P, cn2 > 0 ? cn2 : 1.0, rel, so);
+            const double s = combine(ctx, W, chir[j], action_k(chir[j], m3[j], m4[j], mo[j]), phi[j], out[j],
+                                     accumulate ? accumulate[j] : 0);
+            if (S) S[j] = s;
+            const double te = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+            fill_info(info ? &info[j] : nullptr, so, tb + te);
+            if (!so.ok) worst = EOFA_ENOCONV;
+        }
+    }
+    collect_timing(ctx);
+    if (worst != EOFA_OK && ctx->err.empty()) ctx->err = "a batched solve did not reach tol within max_iter";
+    return worst;
 }
 
 // nrep launches of the fused hop (A_T^{-1} epilogue) alternating parities on workspace buffers,
@@ -607,18 +895,30 @@ std::vector<Sched> sched_candidates(const eofa_ctx* ctx) {
     const Geom& g = ctx->g;
     const long lanes_line = (long)g.Lxh * g.Ly * ctx->Ns;  // lanes of one (z, t) line
     const int nyb = (lanes_line % 256 == 0) ? (int)(lanes_line / 256) : 0;
-    for (int x = 0; x < 2; x++) c.push_back(Sched{0, x, 1, 1, 1, nyb > 0 ? nyb : 1});
+    for (int x = 0; x < 2; x++) c.push_back(Sched{0, x, 1, 1, 1, nyb > 0 ? nyb : 1, 0});
     if (nyb == 0) return c;
     const int opts[] = {1, 2, 4, 8, 16};
-    for (int x = 0; x < 2; x++)
+    for (int x = 0; x < 2; x++) {
+        // small 3D tiles, yb fastest
         for (int ty : opts)
             for (int tz : opts)
                 for (int tt : opts) {
                     if (nyb % ty || g.Lz % tz || g.Lt % tt) continue;
                     const int per = ty * tz * tt;
                     if (per < 16 || per > 128) continue;
-                    c.push_back(Sched{1, x, ty, tz, tt, nyb});
+                    c.push_back(Sched{1, x, ty, tz, tt, nyb, 0});
                 }
+        // long tiles through yb with a small (z, t) patch visited fastest: the yb-neighbour rows stay within
+        // one patch of the L2 window, z/t neighbours inside the patch
+        for (int ty : {nyb, nyb / 2, nyb / 4})
+            for (int tz : opts)
+                for (int tt : opts) {
+                    if (ty < 1 || nyb % ty || g.Lz % tz || g.Lt % tt) continue;
+                    const int pz = tz * tt;
+                    if (pz < 4 || pz > 64) continue;
+                    c.push_back(Sched{1, x, ty, tz, tt, nyb, 1});
+                }
+    }
     return c;
 }
 
@@ -727,9 +1027,9 @@ eofa_status eofa_create(eofa_ctx** out, const int dims[4], int Ns, double m0, co
         ctx->nh = (size_t)(V / 2) * 12 * Ns;
         const size_t maxblk = (ctx->nh + 255) / 256 + 1024;
         HIPCHK(hipMalloc(&ctx->partials, sizeof(double) * maxblk));
-        HIPCHK(hipMalloc(&ctx->scal, sizeof(double) * (SC_N + 256)));
-        HIPCHK(hipMemset(ctx->scal, 0, sizeof(double) * (SC_N + 256)));
-        HIPCHK(hipHostMalloc(&ctx->hscal, sizeof(double) * SC_N, hipHostMallocDefault));
+        HIPCHK(hipMalloc(&ctx->scal, sizeof(double) * SCAL_TOTAL));
+        HIPCHK(hipMemset(ctx->scal, 0, sizeof(double) * SCAL_TOTAL));
+        HIPCHK(hipHostMalloc(&ctx->hscal, sizeof(double) * SCAL_TOTAL, hipHostMallocDefault));
         return EOFA_OK;
     });
     if (st != EOFA_OK) {
@@ -743,8 +1043,7 @@ eofa_status eofa_create(eofa_ctx** out, const int dims[4], int Ns, double m0, co
 
 eofa_status eofa_workspace_size(const eofa_ctx* cctx, const eofa_solve_params* params, int nrhs, size_t* bytes) {
     if (!cctx || !bytes || nrhs < 1) return EOFA_EINVAL;
-    *bytes = needed_bytes(cctx, params) * (size_t)1;
-    (void)nrhs;
+    *bytes = needed_bytes(cctx, params, nrhs);
     return EOFA_OK;
 }
 
@@ -799,16 +1098,7 @@ eofa_status eofa_chiral_action_batch(eofa_ctx* ctx, int n, const int* chir, cons
                                      const eofa_solve_params* params, eofa_solve_info* info) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(n >= 0 && chir && m3 && m4 && mo && phi && out, EOFA_EINVAL, "bad batch arguments");
-        eofa_status worst = EOFA_OK;
-        for (int j = 0; j < n; j++) {
-            double s = 0;
-            eofa_status a = chiral_impl(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j], 0, &s, params,
-                                        info ? &info[j] : nullptr);
-            if (S) S[j] = s;
-            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
-            if (a != EOFA_OK) worst = a;
-        }
-        return worst;
+        return chiral_batch_impl(ctx, n, chir, m3, m4, mo, phi, out, nullptr, S, params, info);
     });
 }
 
@@ -816,14 +1106,23 @@ eofa_status eofa_hinv_batch(eofa_ctx* ctx, int n, const double* m_lo, const doub
                             void* const* out, double* S, const eofa_solve_params* params, eofa_solve_info* info) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(n >= 0 && m_lo && m_hi && phi && out, EOFA_EINVAL, "bad batch arguments");
-        eofa_status worst = EOFA_OK;
+        std::vector<int> chir(2 * n), acc(2 * n);
+        std::vector<double> a3(2 * n), a4(2 * n), ao(2 * n), s2(2 * n);
+        std::vector<const void*> f(2 * n);
+        std::vector<void*> o(2 * n);
         for (int j = 0; j < n; j++) {
-            eofa_status a = eofa_hinv(ctx, m_lo[j], m_hi[j], phi[j], out[j], S ? &S[j] : nullptr, params,
-                                      info ? &info[2 * j] : nullptr);
-            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
-            if (a != EOFA_OK) worst = a;
+            REQUIRE(m_lo[j] > 0 && m_lo[j] <= m_hi[j] && m_hi[j] <= 1, EOFA_EINVAL, "need 0 < m_lo <= m_hi <= 1");
+            // - action (m_lo,m_lo)/(m_lo,m_hi) writes out, then + action (m_lo,m_hi)/(m_hi,m_hi) adds to it
+            chir[2 * j] = -1; a3[2 * j] = m_lo[j]; a4[2 * j] = m_lo[j]; ao[2 * j] = m_hi[j]; acc[2 * j] = 0;
+            chir[2 * j + 1] = +1; a3[2 * j + 1] = m_lo[j]; a4[2 * j + 1] = m_hi[j]; ao[2 * j + 1] = m_hi[j]; acc[2 * j + 1] = 1;
+            f[2 * j] = f[2 * j + 1] = phi[j];
+            o[2 * j] = o[2 * j + 1] = out[j];
         }
-        return worst;
+        eofa_status st = chiral_batch_impl(ctx, 2 * n, chir.data(), a3.data(), a4.data(), ao.data(), f.data(), o.data(),
+                                           acc.data(), s2.data(), params, info);
+        if (S)
+            for (int j = 0; j < n; j++) S[j] = s2[2 * j] + s2[2 * j + 1];
+        return st;
     });
 }
 
@@ -912,7 +1211,7 @@ eofa_status eofa_dslash_bench(eofa_ctx* ctx, int prec, int nrep, double* ms, dou
     });
 }
 
-eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[6], double* best_ms, double* base_ms) {
+eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[7], double* best_ms, double* base_ms) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
         REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
@@ -933,7 +1232,7 @@ eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[6], d
         ctx->tuned_ms[k] = best;
         if (sched_out) {
             sched_out[0] = bs.mode; sched_out[1] = bs.xcd; sched_out[2] = bs.ty;
-            sched_out[3] = bs.tz; sched_out[4] = bs.tt; sched_out[5] = bs.nyb;
+            sched_out[3] = bs.tz; sched_out[4] = bs.tt; sched_out[5] = bs.nyb; sched_out[6] = bs.ord;
         }
         if (best_ms) *best_ms = best;
         if (base_ms) *base_ms = base;
@@ -941,14 +1240,15 @@ eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[6], d
     });
 }
 
-eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[6]) {
+eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[7]) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(sched_in, EOFA_EINVAL, "null schedule");
         REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
-        Sched s{sched_in[0], sched_in[1], sched_in[2], sched_in[3], sched_in[4], sched_in[5]};
+        Sched s{sched_in[0], sched_in[1], sched_in[2], sched_in[3], sched_in[4], sched_in[5], sched_in[6]};
         bool ok = false;
         for (const Sched& c : sched_candidates(ctx))
-            ok |= (c.mode == s.mode && c.xcd == s.xcd && c.ty == s.ty && c.tz == s.tz && c.tt == s.tt && c.nyb == s.nyb);
+            ok |= (c.mode == s.mode && c.xcd == s.xcd && c.ty == s.ty && c.tz == s.tz && c.tt == s.tt &&
+                   c.nyb == s.nyb && c.ord == s.ord);
         REQUIRE(ok, EOFA_EINVAL, "schedule not valid for this lattice");
         ctx->sched[prec == EOFA_FP64 ? 0 : 1] = s;
         return EOFA_OK;
@@ -974,6 +1274,7 @@ void eofa_destroy(eofa_ctx* ctx) {
     }
     if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
     if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->partials_mr) (void)hipFree(ctx->partials_mr);
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (auto& e : ctx->ev_pool) {

@@ -44,12 +44,12 @@ template <typename R> __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return 
 // ------------------------------------------------------------------ lane exchange
 // Value of v held by the lane (s + OFF) mod NS of this lane's group of NS lanes.
 template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL> __device__ __forceinline__ double dpp_d(double v) {
     int2 iv = __builtin_bit_cast(int2, v);
-    iv.x = __builtin_amdgcn_update_dpp(0, iv.x, CTRL, 0xF, 0xF, false);
-    iv.y = __builtin_amdgcn_update_dpp(0, iv.y, CTRL, 0xF, 0xF, false);
+    iv.x = __builtin_amdgcn_mov_dpp(iv.x, CTRL, 0xF, 0xF, true);
+    iv.y = __builtin_amdgcn_mov_dpp(iv.y, CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, iv);
 }
 
@@ -260,6 +260,7 @@ enum : int {
     SC_RR0 = 4,     // |r_0|^2 (stop reference)
     SC_DONE = 5,    // 1 when converged (read by graph replays)
     SC_TOL2 = 6,    // stop threshold on |r|^2 / |r_0|^2
+    SC_DONEX = 7,   // multi-RHS: the x/p update of the converged iteration has been applied
     SC_TMP = 8,     // 8..31 free slots for norms
     SC_N = 32
 };
@@ -273,8 +274,14 @@ __device__ __forceinline__ void finish_sum(const Red& rd, double bsum) {
 // Sum partials[0..n) in a fixed order (256 threads) and apply the epilogue.
 __device__ __forceinline__ void finish_partials(const double* partials, unsigned n, double* S, int slot, int epi) {
     __shared__ double lds[4];
-    double s = 0.0;
-    for (unsigned i = threadIdx.x; i < n; i += blockDim.x) s += partials[i];
+    // 8 independent loads in flight per thread; the summation order is fixed
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned i = threadIdx.x;
+    for (; i + 7 * 256 < n; i += 8 * 256)
+#pragma unroll
+        for (int k = 0; k < 8; k++) a[k] += partials[i + k * 256];
+    for (; i < n; i += 256) a[0] += partials[i];
+    double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     s = block_sum256(s, lds);
     if (threadIdx.x == 0) {
         switch (epi) {

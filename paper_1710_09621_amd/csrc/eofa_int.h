@@ -13,8 +13,9 @@ enum : int { HM_LIN = 0, HM_SITE = 1, HM_SCHUR_W = 2, HM_SCHUR_Q = 3, HM_DT = 4,
 // the (xh, y) plane line (nyb workgroups per line).  mode 0: linear.  mode 1: 3D tiles of
 // ty x tz x tt workgroups visited tile by tile.  xcd != 0: every XCD (the 8 L2 domains) gets
 // one contiguous range of the visiting sequence instead of every 8th workgroup.
+// ord = 1 visits each tile with its (z, t) plane fastest and yb slowest.
 struct Sched {
-    int mode, xcd, ty, tz, tt, nyb;
+    int mode, xcd, ty, tz, tt, nyb, ord;
 };
 
 template <typename R> struct HopArgs {
@@ -37,6 +38,34 @@ template <typename R> struct HopArgs {
     Red red;
 };
 
+// Multi-RHS form of the CG-iteration hops: nr independent systems (own fields, own mass tables,
+// own device scalars at scal + r * SC_N) through one launch; the links of each workgroup are
+// staged once and reused by all systems; a system whose SC_DONE is set is skipped.
+constexpr int NRMAX = 8;
+template <typename R> struct HopArgsMR {
+    Geom g;
+    Sched sc;
+    int par, nr;
+    const cpx<R>* Uown;
+    const cpx<R>* Uoth;
+    const cpx<R>* in[NRMAX];
+    cpx<R>* out[NRMAX];
+    cpx<R>* out2[NRMAX];
+    const cpx<R>* aux[NRMAX];
+    const cpx<R>* aux2[NRMAX];
+    const SiteOp* opA[NRMAX];
+    const SiteOp* opB[NRMAX];
+    R cz, caux;
+    double* scal;       // nr blocks of SC_N scalars
+    double* partials;   // partials[r * pstride + block]
+    int pstride;
+    int epi;            // reduction epilogue (EPI_CG_W / EPI_CG_R) for the reducing modes
+};
+template <typename R> hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipStream_t st);
+// x_r += alpha_r p_r ; p_r = r_r + beta_r p_r for the systems whose SC_DONEX is clear, then SC_DONEX = SC_DONE
+template <typename R> hipError_t launch_cg_xp_mr(int nr, cpx<R>* const* x, cpx<R>* const* p, cpx<R>* const* r,
+                                                 double* scal, size_t n, hipStream_t st);
+
 template <typename R> hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st);
 template <typename R> hipError_t launch_site(int Ns, bool dag, const cpx<R>* in, cpx<R>* out, const SiteOp* op, int Vh,
                                              hipStream_t st);
@@ -45,6 +74,8 @@ template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>
 template <typename R> hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red,
                                               hipStream_t st);
 template <typename R> hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st);
+// dst[i] = host_vals[i], i < n <= 64 (values travel as kernel arguments: the host array may die at once)
+hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream_t st);
 // sets S[s_i] = v_i for the slots s_i >= 0 (stream-ordered, no host buffer)
 hipError_t launch_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2, hipStream_t st);
 hipError_t launch_convert_d2f(const cd* in, cpx<float>* out, size_t n, hipStream_t st);

@@ -93,38 +93,54 @@ __device__ __forceinline__ void hop_pipe(cpx<R> acc[12], cpx<R> cur[12], const c
     }
 }
 
-// z = hop(in) at (cb, s).  With HOP_LDS_LINKS the workgroup first stages the 8 links of each of
-// its 256/NS sites in LDS (each link entry read once from global memory instead of once per slice).
+// The 8 links of each of the workgroup's 256/NS sites, staged in LDS: sU[site][l][k], l = 0..3 the
+// forward links U_mu(x), l = 4..7 the backward links U_mu(x - mu).  Each entry is read once from
+// global memory instead of once per slice.  Ends with a workgroup barrier.
+template <int NS, typename R>
+__device__ __forceinline__ void stage_links(cpx<R> (*sU)[8][9], const cpx<R>* __restrict__ Uown,
+                                            const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s) {
+    const int ls = threadIdx.x / NS;
+    for (int e = s; e < 72; e += NS) {
+        const int l = e / 9, k = e % 9;
+        const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k
+                                    : Uoth + ((size_t)nb[2 * (l - 4) + 1] * 4 + (l - 4)) * 9 + k;
+        sU[ls][l][k] = *src;
+    }
+    __syncthreads();
+}
+
+// z = hop(in) at (cb, s) with the links of this lane's site in sUl[8][9].
+template <int NS, bool DAG, typename R>
+__device__ __forceinline__ void hop_lds(cpx<R> z[12], const cpx<R>* __restrict__ in, const cpx<R> (*sUl)[9],
+                                        const int nb[8], int s) {
+#pragma unroll
+    for (int j = 0; j < 12; j++) z[j] = {0, 0};
+    if constexpr (HOP_PIPE) {
+        cpx<R> cur[12];
+        load_spinor<NS>(cur, in, nb[0], s);
+        hop_pipe<NS, DAG, 0>(z, cur, in, sUl, nb, s);
+    } else {
+        hop_mu<NS, DAG, 0>(z, in, sUl[0], sUl[4], nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 1>(z, in, sUl[1], sUl[5], nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 2>(z, in, sUl[2], sUl[6], nb, s);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 3>(z, in, sUl[3], sUl[7], nb, s);
+    }
+}
+
+// z = hop(in) at (cb, s).  With HOP_LDS_LINKS the workgroup first stages its sites' links in LDS.
 template <int NS, bool DAG, typename R>
 __device__ __forceinline__ void hop_all(cpx<R> z[12], const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ Uown,
                                         const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s) {
-#pragma unroll
-    for (int j = 0; j < 12; j++) z[j] = {0, 0};
     if constexpr (HOP_LDS_LINKS && NS >= 8) {
-        constexpr int SITES = 256 / NS;
-        __shared__ cpx<R> sU[SITES][8][9];
-        const int ls = threadIdx.x / NS;  // local site of this lane
-        for (int e = s; e < 72; e += NS) {
-            const int l = e / 9, k = e % 9;
-            const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k
-                                        : Uoth + ((size_t)nb[2 * (l - 4) + 1] * 4 + (l - 4)) * 9 + k;
-            sU[ls][l][k] = *src;
-        }
-        __syncthreads();
-        if constexpr (HOP_PIPE) {
-            cpx<R> cur[12];
-            load_spinor<NS>(cur, in, nb[0], s);
-            hop_pipe<NS, DAG, 0>(z, cur, in, sU[ls], nb, s);
-            return;
-        }
-        hop_mu<NS, DAG, 0>(z, in, sU[ls][0], sU[ls][4], nb, s);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 1>(z, in, sU[ls][1], sU[ls][5], nb, s);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 2>(z, in, sU[ls][2], sU[ls][6], nb, s);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 3>(z, in, sU[ls][3], sU[ls][7], nb, s);
+        __shared__ cpx<R> sU[256 / NS][8][9];
+        stage_links<NS>(sU, Uown, Uoth, cb, nb, s);
+        hop_lds<NS, DAG>(z, in, sU[threadIdx.x / NS], nb, s);
     } else {
+#pragma unroll
+        for (int j = 0; j < 12; j++) z[j] = {0, 0};
         hop_mu<NS, DAG, 0>(z, in, Uown + ((size_t)cb * 4 + 0) * 9, Uoth + ((size_t)nb[1] * 4 + 0) * 9, nb, s);
         HOP_FENCE();
         hop_mu<NS, DAG, 1>(z, in, Uown + ((size_t)cb * 4 + 1) * 9, Uoth + ((size_t)nb[3] * 4 + 1) * 9, nb, s);
@@ -157,7 +173,9 @@ __device__ __forceinline__ int tile_of(int b, int n, const Sched& sc, const Geom
         const int per = sc.ty * sc.tz * sc.tt;
         const int intra = b % per, tile = b / per;
         const int nyt = sc.nyb / sc.ty, nzt = g.Lz / sc.tz;
-        const int yy = intra % sc.ty, zz = (intra / sc.ty) % sc.tz, tq = intra / (sc.ty * sc.tz);
+        int yy, zz, tq;
+        if (sc.ord) { zz = intra % sc.tz; tq = (intra / sc.tz) % sc.tt; yy = intra / (sc.tz * sc.tt); }
+        else { yy = intra % sc.ty; zz = (intra / sc.ty) % sc.tz; tq = intra / (sc.ty * sc.tz); }
         const int ty = tile % nyt, tz = (tile / nyt) % nzt, tt = tile / (nyt * nzt);
         const int yb = ty * sc.ty + yy, z = tz * sc.tz + zz, t = tt * sc.tt + tq;
         b = yb + sc.nyb * (z + g.Lz * t);
@@ -246,6 +264,110 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
         if (!valid) nrm = 0.0;
         finish_sum(a.red, block_sum256(nrm, lds));
     }
+}
+
+// ===================================================================== multi-RHS hop
+template <int NS, bool DAG, int MODE, typename R>
+__global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a) {
+    const int tid = tile_of(blockIdx.x, gridDim.x, a.sc, a.g) * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int s = lane & (NS - 1);
+    int cb = tid / NS;
+    const bool valid = cb < a.g.Vh;
+    if (!valid) cb = a.g.Vh - 1;
+    int nb[8];
+    neighbours(a.g, cb, a.par, nb);
+    __shared__ cpx<R> sU[256 / NS][8][9];
+    __shared__ double lds[4];
+    stage_links<NS>(sU, a.Uown, a.Uoth, cb, nb, s);
+    const size_t base = (size_t)cb * 12 * NS + s;
+    for (int r = 0; r < a.nr; r++) {
+        const double* S = a.scal + r * SC_N;
+        if (S[SC_DONE] != 0.0) continue;  // uniform over the grid
+        cpx<R> z[12], v[12];
+        hop_lds<NS, DAG>(z, a.in[r], sU[threadIdx.x / NS], nb, s);
+        double nrm = 0.0;
+        if constexpr (MODE == HM_SITE) {
+#pragma unroll
+            for (int j = 0; j < 12; j++) v[j] = cscale(a.cz, z[j]);
+            site_op<NS, DAG>(v, *a.opA[r], s, lane);
+        } else if constexpr (MODE == HM_SCHUR_W) {
+            site_op<NS, false>(z, *a.opA[r], s, lane);
+            const cpx<R>* aux = a.aux[r] + base;
+#pragma unroll
+            for (int j = 0; j < 12; j++) {
+                cpx<R> t = aux[j * NS];
+                v[j].x = fma(a.cz, z[j].x, a.caux * t.x);
+                v[j].y = fma(a.cz, z[j].y, a.caux * t.y);
+            }
+        } else {  // HM_SCHUR_Q
+            const R alpha = (R)S[SC_ALPHA];
+            const cpx<R>* aux = a.aux[r] + base;
+            const cpx<R>* aux2 = a.aux2[r] + base;
+#pragma unroll
+            for (int j = 0; j < 12; j++) {
+                cpx<R> w = aux[j * NS], rr = aux2[j * NS];
+                R qx = fma(a.cz, z[j].x, a.caux * w.x), qy = fma(a.cz, z[j].y, a.caux * w.y);
+                v[j].x = fma(-alpha, qx, rr.x);
+                v[j].y = fma(-alpha, qy, rr.y);
+            }
+        }
+        if (valid) {
+            cpx<R>* out = a.out[r] + base;
+#pragma unroll
+            for (int j = 0; j < 12; j++) out[j * NS] = v[j];
+        }
+        if constexpr (MODE != HM_SITE) {
+#pragma unroll
+            for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+            if (!valid) nrm = 0.0;
+            if constexpr (MODE == HM_SCHUR_W) {
+                site_op<NS, true>(v, *a.opB[r], s, lane);
+                if (valid) {
+                    cpx<R>* o2 = a.out2[r] + base;
+#pragma unroll
+                    for (int j = 0; j < 12; j++) o2[j * NS] = v[j];
+                }
+            }
+            const double bs = block_sum256(nrm, lds);
+            if (threadIdx.x == 0) a.partials[(size_t)r * a.pstride + blockIdx.x] = bs;
+        }
+    }
+}
+
+// one block per system: finish the reduction of system r (skipped once it is done)
+__global__ __launch_bounds__(256) void k_finish_mr(const double* __restrict__ partials, int pstride, unsigned n,
+                                                   double* scal, int epi) {
+    double* S = scal + blockIdx.x * SC_N;
+    if (S[SC_DONE] != 0.0) return;
+    finish_partials(partials + (size_t)blockIdx.x * pstride, n, S, 0, epi);
+}
+
+template <typename R> struct XpArgs {
+    cpx<R>* x[NRMAX];
+    cpx<R>* p[NRMAX];
+    cpx<R>* r[NRMAX];
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_cg_xp_mr(const XpArgs<R> a, double* scal, size_t n) {
+    const int r = blockIdx.y;
+    const double* S = scal + r * SC_N;
+    if (S[SC_DONEX] != 0.0) return;
+    const R alpha = (R)S[SC_ALPHA], beta = (R)S[SC_BETA];
+    cpx<R>* x = a.x[r];
+    cpx<R>* p = a.p[r];
+    const cpx<R>* rr = a.r[r];
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        cpx<R> pp = p[i], q = rr[i], xx = x[i];
+        xx.x = fma(alpha, pp.x, xx.x); xx.y = fma(alpha, pp.y, xx.y);
+        pp.x = fma(beta, pp.x, q.x);   pp.y = fma(beta, pp.y, q.y);
+        x[i] = xx; p[i] = pp;
+    }
+}
+
+__global__ void k_sync_done(double* scal, int nr) {
+    if (threadIdx.x < nr) scal[threadIdx.x * SC_N + SC_DONEX] = scal[threadIdx.x * SC_N + SC_DONE];
 }
 
 // ===================================================================== site-local op only
@@ -449,6 +571,13 @@ __global__ __launch_bounds__(256) void k_combine(const cd* __restrict__ phi, con
     finish_sum(red, block_sum256(acc, lds));
 }
 
+struct Vec64 {
+    double v[64];
+};
+__global__ void k_set_vec(double* dst, int n, const Vec64 vals) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = vals.v[threadIdx.x];
+}
+
 __global__ void k_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2) {
     if (threadIdx.x == 0) {
         if (s0 >= 0) S[s0] = v0;
@@ -506,6 +635,50 @@ template hipError_t launch_hop<double>(int, bool, int, bool, const HopArgs<doubl
 template hipError_t launch_hop<float>(int, bool, int, bool, const HopArgs<float>&, hipStream_t);
 
 template <typename R>
+hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipStream_t st) {
+    if (a.nr < 1 || a.nr > NRMAX) return hipErrorInvalidValue;
+    const int grid = (int)(((size_t)a.g.Vh * Ns + 255) / 256);
+    if (grid > a.pstride) return hipErrorInvalidValue;
+#define MR_L(D, M) hipLaunchKernelGGL((k_hop_mr<NS, D, M, R>), dim3(grid), dim3(256), 0, st, a)
+#define MR_MODES(D)                                            \
+    switch (mode) {                                            \
+    case HM_SITE: MR_L(D, HM_SITE); break;                     \
+    case HM_SCHUR_W: MR_L(D, HM_SCHUR_W); break;               \
+    case HM_SCHUR_Q: MR_L(D, HM_SCHUR_Q); break;               \
+    default: return hipErrorInvalidValue;                      \
+    }
+    switch (Ns) {
+    case 8: { constexpr int NS = 8; if (dag) { MR_MODES(true) } else { MR_MODES(false) } break; }
+    case 16: { constexpr int NS = 16; if (dag) { MR_MODES(true) } else { MR_MODES(false) } break; }
+    case 32: { constexpr int NS = 32; if (dag) { MR_MODES(true) } else { MR_MODES(false) } break; }
+    default: return hipErrorInvalidValue;
+    }
+#undef MR_MODES
+#undef MR_L
+    if (mode != HM_SITE)
+        hipLaunchKernelGGL(k_finish_mr, dim3(a.nr), dim3(256), 0, st, a.partials, a.pstride, (unsigned)grid, a.scal,
+                           a.epi);
+    return hipGetLastError();
+}
+template hipError_t launch_hop_mr<double>(int, bool, int, const HopArgsMR<double>&, hipStream_t);
+template hipError_t launch_hop_mr<float>(int, bool, int, const HopArgsMR<float>&, hipStream_t);
+
+template <typename R>
+hipError_t launch_cg_xp_mr(int nr, cpx<R>* const* x, cpx<R>* const* p, cpx<R>* const* r, double* scal, size_t n,
+                           hipStream_t st) {
+    if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
+    XpArgs<R> a{};
+    for (int i = 0; i < nr; i++) { a.x[i] = x[i]; a.p[i] = p[i]; a.r[i] = r[i]; }
+    const int gx = nblk(n) > 1024 ? 1024 : nblk(n);
+    hipLaunchKernelGGL((k_cg_xp_mr<R>), dim3(gx, nr), dim3(256), 0, st, a, scal, n);
+    hipLaunchKernelGGL(k_sync_done, dim3(1), dim3(64), 0, st, scal, nr);
+    return hipGetLastError();
+}
+template hipError_t launch_cg_xp_mr<double>(int, cd* const*, cd* const*, cd* const*, double*, size_t, hipStream_t);
+template hipError_t launch_cg_xp_mr<float>(int, cpx<float>* const*, cpx<float>* const*, cpx<float>* const*, double*,
+                                           size_t, hipStream_t);
+
+template <typename R>
 hipError_t launch_site(int Ns, bool dag, const cpx<R>* in, cpx<R>* out, const SiteOp* op, int Vh, hipStream_t st) {
     const int grid = (int)(((size_t)Vh * Ns + 255) / 256);
     NS_SWITCH(Ns, if (dag) hipLaunchKernelGGL((k_site<NS, true, R>), dim3(grid), dim3(256), 0, st, in, out, op, Vh);
@@ -542,6 +715,14 @@ hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t s
 }
 template hipError_t launch_norm2<double>(const cd*, size_t, const Red&, hipStream_t);
 template hipError_t launch_norm2<float>(const cpx<float>*, size_t, const Red&, hipStream_t);
+
+hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream_t st) {
+    if (n < 0 || n > 64) return hipErrorInvalidValue;
+    Vec64 v{};
+    for (int i = 0; i < n; i++) v.v[i] = host_vals[i];
+    hipLaunchKernelGGL(k_set_vec, dim3(1), dim3(64), 0, st, dst, n, v);
+    return hipGetLastError();
+}
 
 hipError_t launch_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2, hipStream_t st) {
     hipLaunchKernelGGL(k_scal_set, dim3(1), dim3(64), 0, st, S, s0, v0, s1, v1, s2, v2);

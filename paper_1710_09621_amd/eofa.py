@@ -249,13 +249,13 @@ class Context:
         """Pick the hop schedule for this lattice; cache: JSON path keyed by (dims, Ns, prec, arch)."""
         import json
         key = f"{'x'.join(map(str, self.dims))}_Ns{self.Ns}_p{int(prec)}_{self._arch()}"
-        sched = (C.c_int * 6)()
+        sched = (C.c_int * 7)()
         self._prep_ws(params(prec=prec))
         if cache and os.path.exists(cache):
             try:
                 with open(cache) as f:
                     entry = json.load(f).get(key)
-                if entry:
+                if entry and len(entry.get("sched", [])) == 7:
                     sched[:] = entry["sched"]
                     if self.lib.eofa_set_schedule(self.h, int(prec), sched) == OK:
                         return dict(entry, cached=True)
@@ -284,6 +284,23 @@ class Context:
             return self.torch.cuda.get_device_properties(self.device).gcnArchName.split(":")[0]
         except Exception:
             return "gfx"
+
+    def hinv_batch(self, pairs, phis, p=None):
+        """pairs: list of (m_lo, m_hi); phis: list of 4D sources; returns a Result per source."""
+        p = p or params()
+        n = len(pairs)
+        phis = [self._c128(f, self.shape4) for f in phis]
+        outs = [self.torch.empty_like(f) for f in phis]
+        self._prep_ws(p, 2 * n)
+        mlo = (C.c_double * n)(*[float(a[0]) for a in pairs])
+        mhi = (C.c_double * n)(*[float(a[1]) for a in pairs])
+        pin = (C.c_void_p * n)(*[f.data_ptr() for f in phis])
+        pout = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        S = (C.c_double * n)()
+        info = (SolveInfo * (2 * n))()
+        st = self.lib.eofa_hinv_batch(self.h, n, mlo, mhi, pin, pout, S, C.byref(p), info)
+        self._check(st, "hinv_batch")
+        return [Result(outs[j], S[j], [info[2 * j].as_dict(), info[2 * j + 1].as_dict()]) for j in range(n)]
 
     def hop_timing(self, enable=True):
         ms, n, b = C.c_double(), C.c_long(), C.c_double()
