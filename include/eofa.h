@@ -178,8 +178,42 @@ eofa_status eofa_autotune(eofa_ctx *ctx, int prec, int nrep, int sched_out[7], d
 /* Re-install a schedule returned by eofa_autotune (EINVAL if it does not fit this lattice). */
 eofa_status eofa_set_schedule(eofa_ctx *ctx, int prec, const int sched_in[7]);
 
-/* Learned preconditioner weights: the packed BF16 blob produced by eofa_cnn_* (see below). */
-eofa_status eofa_set_precond(eofa_ctx *ctx, const void *weights_dev, size_t bytes);
+/*
+ * Learned preconditioner (solves with params->pc = EOFA_PC_LEARNED; Ns must be a multiple of 8).
+ * A 4-layer network of 3^4 convolutions, 24 -> 32 -> 32 -> 32 -> 24 channels (spin x colour as
+ * re/im), applied to the odd-site residual of the even-odd system one s-slice at a time with the
+ * weights shared over s, on the checkerboard-compressed 4D lattice (xh, y, z, t) with periodic wrap.
+ * It maps v to |v| N(v / |v|) and approximates (Dhat^dag Dhat)^{-1}; flexible GCR on Dhat uses
+ * z = N(Dhat^dag r) as its right preconditioner.  When GCR stalls (less than 2x in |r| over 20
+ * iterations) or breaks down, the solve falls back to CG on the remaining defect (info.fell_back = 1).
+ * Parameters: EOFA_CNN_NPARAM FP32 values, layer by layer: weights [81 taps][32 out][32 in] (tap =
+ * 27(dt+1) + 9(dz+1) + 3(dy+1) + (dx+1)), then 32 biases; entries of padded channels are ignored.
+ */
+#define EOFA_CNN_NPARAM (4 * (81 * 32 * 32 + 32))
+/* Install parameters from host memory (count = EOFA_CNN_NPARAM); relu != 0 puts a ReLU after
+ * layers 1-3 (0: linear network).  Resets the Adam state. */
+eofa_status eofa_set_precond(eofa_ctx *ctx, const float *params_host, size_t count, int relu);
+/* Random (He-normal, seeded) parameters; relu != 0 puts a ReLU after layers 1-3 (default: linear). */
+eofa_status eofa_cnn_init(eofa_ctx *ctx, unsigned long long seed, int relu);
+/* Copy the current parameters to host memory (count = EOFA_CNN_NPARAM). */
+eofa_status eofa_cnn_params(eofa_ctx *ctx, float *params_host, size_t count);
+/* out5 = |r| N(r / |r|) on the odd sites of the canonical 5D field in5 (even sites of out5 = 0). */
+eofa_status eofa_cnn_apply(eofa_ctx *ctx, const void *in5, void *out5);
+/*
+ * One training pair (canonical 5D fields, odd sites used): input rho5 / |rho5|, target e5 / |rho5|,
+ * loss |N - T|^2 / |T|^2 (*loss).  grad_host (may be NULL) receives dloss/dparam * |T|^2 / 2 as
+ * EOFA_CNN_NPARAM floats; lr > 0 then takes one Adam step (beta = 0.9, 0.999) with that gradient.
+ */
+eofa_status eofa_cnn_train_step(eofa_ctx *ctx, const void *rho5, const void *e5, double lr, double *loss,
+                                float *grad_host);
+/*
+ * Training pairs from the method's own CG: one CG solve of Dhat(m_plus, m_minus) x = b with a seeded
+ * Gaussian b on the odd sites, snapshots x_k at k = 2, 4, 8, ... (n <= 16), then e_k = x* - x_k and
+ * rho_k = Dhat^dag Dhat e_k, written to rho5[i] / e5[i] (canonical 5D device buffers, even sites zero).
+ * *made = number of pairs written (fewer than n when CG converged early).
+ */
+eofa_status eofa_training_pairs(eofa_ctx *ctx, double m_plus, double m_minus, unsigned long long seed, int n,
+                                void *const *rho5, void *const *e5, int *made);
 
 const char *eofa_last_error(const eofa_ctx *ctx);
 void eofa_destroy(eofa_ctx *ctx);

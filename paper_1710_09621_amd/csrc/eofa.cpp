@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/eofa.h"
+#include "cnn.h"
 #include "eofa_int.h"
 
 using namespace eofa;
@@ -56,6 +57,18 @@ struct eofa_ctx {
     double hop_ms = 0;
     long hop_launches = 0;
     double hop_bytes = 0;
+    // learned preconditioner (see cnn.hip)
+    struct Cnn {
+        bool ready = false;
+        int relu = 0;
+        float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;  // CNN_NPARAM each
+        unsigned short *Wb = nullptr, *Wt = nullptr;                    // bf16 forward / backward-data weights
+        int rows = 0;
+        unsigned short *X0 = nullptr, *A[3] = {nullptr, nullptr, nullptr}, *dYb = nullptr, *XT = nullptr, *dYT = nullptr;
+        float *Y = nullptr, *T = nullptr, *dY = nullptr, *dA = nullptr, *part = nullptr;
+        long step = 0;
+    } cnn;
+    double* dots = nullptr;  // FGCR dot products (device)
     // workgroup schedules of the hop kernels, per storage precision (0: FP64, 1: FP32); set by the autotuner
     Sched sched[2] = {{0, 0, 1, 1, 1, 1, 0}, {0, 0, 1, 1, 1, 1, 0}};
     double tuned_ms[2] = {0, 0};
@@ -145,11 +158,20 @@ size_t batch_sys_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
     return 2 * align_up(ctx->nh * sizeof(cd)) + 7 * align_up(ctx->nh * kr);
 }
 
+constexpr int FGCR_M = 8;  // directions kept before a restart
+
+size_t fgcr_bytes(const eofa_ctx* ctx) { return (2 * FGCR_M + 1) * align_up(ctx->nh * sizeof(cd)); }
+
+// workspace: FP64 set | FP32 set (mixed) | then either the FGCR directions or the batched systems
+size_t base_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
+    return work64_bytes(ctx) + ((p && p->prec != EOFA_FP64) ? work32_bytes(ctx) : 0);
+}
+
 size_t needed_bytes(const eofa_ctx* ctx, const eofa_solve_params* p, int nrhs = 1) {
-    size_t b = work64_bytes(ctx);
-    if (p && p->prec != EOFA_FP64) b += work32_bytes(ctx);
-    if (nrhs > 1 && ctx->Ns >= 8) b += (size_t)std::min(nrhs, NRMAX) * batch_sys_bytes(ctx, p);
-    return b;
+    size_t extra = 0;
+    if (p && p->pc == EOFA_PC_LEARNED) extra = fgcr_bytes(ctx);
+    if (nrhs > 1 && ctx->Ns >= 8) extra = std::max(extra, (size_t)std::min(nrhs, NRMAX) * batch_sys_bytes(ctx, p));
+    return base_bytes(ctx, p) + extra;
 }
 
 void ensure_ws(eofa_ctx* ctx, size_t need) {
@@ -331,6 +353,27 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
     return o;
 }
 
+void ensure_partials_mr(eofa_ctx* ctx) {
+    // batch kernels: one partial per 256 sites x s; launch_mdot: up to 1024 blocks
+    const int need = std::max((int)(((size_t)ctx->g.Vh * ctx->Ns + 255) / 256) + 1, 1024);
+    if (ctx->partials_mr && ctx->pstride >= need) return;
+    if (ctx->partials_mr) HIPCHK(hipFree(ctx->partials_mr));
+    // rows: NRMAX systems of the batch kernels, or 2 x 9 (re, im) dot products of launch_mdot
+    HIPCHK(hipMalloc(&ctx->partials_mr, sizeof(double) * (size_t)need * (NRMAX > 18 ? NRMAX : 18)));
+    ctx->pstride = need;
+}
+
+double norm2_half(eofa_ctx* ctx, const cd* v) {
+    HIPCHK(launch_norm2<double>(v, ctx->nh, red_of(ctx, SC_TMP + 9, EPI_STORE), ctx->st));
+    sync_scal(ctx);
+    return ctx->hscal[SC_TMP + 9];
+}
+
+int auto_check_every_n(const eofa_ctx* ctx) {
+    const double sites = (double)ctx->nh;
+    return sites >= 4e6 ? 1 : (sites >= 1e6 ? 4 : 16);
+}
+
 // ------------------------------------------------------------------ mixed precision CG
 // FP64 normal residual r = Dhat^dag (bh - Dhat x) into W.r; returns |r|^2 (host sync).
 double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const cd* bh, const SiteOp* Ai,
@@ -414,9 +457,215 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
     return o;
 }
 
+// ------------------------------------------------------------------ learned preconditioner (host side)
+void cnn_alloc(eofa_ctx* ctx) {
+    auto& c = ctx->cnn;
+    const int rows = ctx->g.Vh * ctx->Ns;
+    if (!c.P) {
+        for (float** q : {&c.P, &c.G, &c.M, &c.V}) {
+            HIPCHK(hipMalloc(q, sizeof(float) * CNN_NPARAM));
+            HIPCHK(hipMemsetAsync(*q, 0, sizeof(float) * CNN_NPARAM, ctx->st));
+        }
+        HIPCHK(hipMalloc(&c.Wb, sizeof(unsigned short) * CNN_LAYERS * CNN_WSZ));
+        HIPCHK(hipMalloc(&c.Wt, sizeof(unsigned short) * CNN_LAYERS * CNN_WSZ));
+    }
+    if (c.rows != rows) {
+        for (void* q : {(void*)c.X0, (void*)c.A[0], (void*)c.A[1], (void*)c.A[2], (void*)c.dYb, (void*)c.XT,
+                        (void*)c.dYT, (void*)c.Y, (void*)c.T, (void*)c.dY, (void*)c.dA, (void*)c.part})
+            if (q) HIPCHK(hipFree(q));
+        const size_t r32 = (size_t)rows * 32;
+        for (unsigned short** q : {&c.X0, &c.A[0], &c.A[1], &c.A[2], &c.dYb, &c.XT, &c.dYT})
+            HIPCHK(hipMalloc(q, sizeof(unsigned short) * r32));
+        for (float** q : {&c.Y, &c.T, &c.dY, &c.dA}) HIPCHK(hipMalloc(q, sizeof(float) * r32));
+        HIPCHK(hipMalloc(&c.part, sizeof(float) * (size_t)cnn_wgrad_chunks(rows) * 81 * 1024));
+        c.rows = rows;
+    }
+}
+
+// bf16 copies of the weights for the forward and backward-data convolutions
+void cnn_refresh(eofa_ctx* ctx) {
+    auto& c = ctx->cnn;
+    for (int l = 0; l < CNN_LAYERS; l++) {
+        HIPCHK(cnn_f32_to_bf16(c.P + (size_t)l * CNN_LSZ, c.Wb + (size_t)l * CNN_WSZ, CNN_WSZ, ctx->st));
+        HIPCHK(cnn_w_transpose(c.P + (size_t)l * CNN_LSZ, c.Wt + (size_t)l * CNN_WSZ, ctx->st));
+    }
+}
+
+// X0 -> Y through the four layers
+void cnn_forward_rows(eofa_ctx* ctx) {
+    auto& c = ctx->cnn;
+    const unsigned short* in = c.X0;
+    for (int l = 0; l < CNN_LAYERS; l++) {
+        const bool last = (l == CNN_LAYERS - 1);
+        void* out = last ? (void*)c.Y : (void*)c.A[l];
+        HIPCHK(cnn_conv_fwd(in, c.Wb + (size_t)l * CNN_WSZ, c.P + (size_t)l * CNN_LSZ + CNN_WSZ, out, last, ctx->g,
+                            ctx->Ns, last ? 0 : c.relu, ctx->st));
+        if (!last) in = c.A[l];
+    }
+}
+
+// out = |in| N(in / |in|) on odd half fields (FP64); slot SC_TMP+12 holds |in|^2
+void cnn_apply_half(eofa_ctx* ctx, const cd* in, cd* out) {
+    auto& c = ctx->cnn;
+    double* n2 = ctx->scal + SC_TMP + 12;
+    HIPCHK(launch_norm2<double>(in, ctx->nh, red_of(ctx, SC_TMP + 12, EPI_STORE), ctx->st));
+    HIPCHK(cnn_half_to_rows(in, c.X0, ctx->g, ctx->Ns, n2, 1, ctx->st));
+    cnn_forward_rows(ctx);
+    HIPCHK(cnn_rows_to_half(c.Y, out, ctx->g, ctx->Ns, n2, ctx->st));
+}
+
+// Loss and gradient for one (rho, e) pair: input rho/|rho|, target e/|rho|, L = |N - T|^2 / |T|^2.
+// Gradients go to c.G (dL/dparam scaled by |T|^2 / 2).  Returns L.
+double cnn_grad(eofa_ctx* ctx, const cd* rho, const cd* e) {
+    auto& c = ctx->cnn;
+    const int rows = c.rows;
+    const size_t r32 = (size_t)rows * 32;
+    double* n2 = ctx->scal + SC_TMP + 12;
+    HIPCHK(launch_norm2<double>(rho, ctx->nh, red_of(ctx, SC_TMP + 12, EPI_STORE), ctx->st));
+    HIPCHK(cnn_half_to_rows(rho, c.X0, ctx->g, ctx->Ns, n2, 1, ctx->st));
+    HIPCHK(cnn_half_to_rows_f32(e, c.T, ctx->g, ctx->Ns, n2, ctx->st));
+    cnn_forward_rows(ctx);
+    HIPCHK(cnn_mse(c.Y, c.T, c.dY, r32, 1.0f, red_of(ctx, SC_TMP + 13, EPI_STORE), ctx->st));
+    HIPCHK(launch_norm2<float>((const cpx<float>*)c.T, r32 / 2, red_of(ctx, SC_TMP + 14, EPI_STORE), ctx->st));
+    const float* dcur = c.dY;
+    for (int l = CNN_LAYERS - 1; l >= 0; l--) {
+        const unsigned short* in = (l == 0) ? c.X0 : c.A[l - 1];
+        HIPCHK(cnn_to_chmajor(dcur, true, c.dYT, rows, ctx->st));
+        HIPCHK(cnn_to_chmajor(in, false, c.XT, rows, ctx->st));
+        HIPCHK(cnn_wgrad(c.dYT, c.XT, c.part, c.G + (size_t)l * CNN_LSZ, ctx->g, ctx->Ns, CNN_CIN[l], CNN_COUT[l], ctx->st));
+        HIPCHK(cnn_bgrad(dcur, rows, c.G + (size_t)l * CNN_LSZ + CNN_WSZ, CNN_COUT[l], ctx->st));
+        if (l > 0) {
+            HIPCHK(cnn_f32_to_bf16(dcur, c.dYb, r32, ctx->st));
+            HIPCHK(cnn_conv_fwd(c.dYb, c.Wt + (size_t)l * CNN_WSZ, nullptr, c.dA, true, ctx->g, ctx->Ns, 0, ctx->st));
+            if (c.relu) HIPCHK(cnn_relu_bwd(c.dA, c.A[l - 1], r32, ctx->st));
+            dcur = c.dA;
+        }
+    }
+    sync_scal(ctx);
+    const double t2 = ctx->hscal[SC_TMP + 14];
+    return t2 > 0 ? ctx->hscal[SC_TMP + 13] / t2 : 0.0;
+}
+
+// out = Dhat^dag in (odd half fields); scratch W.wt, W.at
+void schur_dag64(eofa_ctx* ctx, const Work64& W, const SiteOp* Ad, const cd* in, cd* out) {
+    HIPCHK(launch_site<double>(ctx->Ns, true, in, W.wt, Ad, ctx->g.Vh, ctx->st));
+    auto c = hop_args<double>(ctx, 0);
+    c.in = W.wt; c.out = W.at; c.opA = Ad; c.cz = 1.0; c.caux = 0.0;
+    hop<double>(ctx, true, HM_SITE, false, c);
+    auto d = hop_args<double>(ctx, 1);
+    d.in = W.at; d.out = out; d.aux = in; d.caux = 1.0; d.cz = -0.25;
+    hop<double>(ctx, true, HM_LIN, false, d);
+}
+
+// out = Dhat in; also W.wt = A^{-dag} out (for a following Dhat^dag); scratch W.u
+void schur64(eofa_ctx* ctx, const Work64& W, const SiteOp* Ai, const SiteOp* Ad, const cd* in, cd* out) {
+    auto a = hop_args<double>(ctx, 0);
+    a.in = in; a.out = W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
+    hop<double>(ctx, false, HM_SITE, false, a);
+    auto b = hop_args<double>(ctx, 1);
+    b.in = W.u; b.out = out; b.out2 = W.wt; b.aux = in; b.opA = Ai; b.opB = Ad; b.cz = -0.25; b.caux = 1.0;
+    b.red = red_of(ctx, SC_TMP + 15, EPI_STORE);
+    hop<double>(ctx, false, HM_SCHUR_W, true, b);
+}
+
+// ------------------------------------------------------------------ flexible GCR with the network
+// Solves Dhat x = bh (odd sites) with the right preconditioner z = N(Dhat^dag r), the network N standing
+// in for (Dhat^dag Dhat)^{-1}: Dhat itself is not positive-real (plain GCR on it stagnates), while
+// Dhat N Dhat^dag is Hermitian positive definite for N = 1 and stays positive-real while N is close
+// to a positive operator.  Truncated GCR keeps the last FGCR_M directions in a ring (each new
+// q = Dhat z made orthogonal to the kept ones by classical Gram-Schmidt, the same combination applied
+// to z).  Falls back to FP64 CG (cg64) on the remaining defect when the residual stops falling (less
+// than 2x in norm over 20 iterations) or on breakdown.
+CgOut fgcr(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, const eofa_solve_params& P,
+           bool* fell_back) {
+    const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+    const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+    const size_t nh = ctx->nh;
+    const size_t hb = align_up(nh * sizeof(cd));
+    char* q0 = ctx->ws + base_bytes(ctx, &P);
+    cd* Z[FGCR_M];
+    cd* Q[FGCR_M];
+    for (int i = 0; i < FGCR_M; i++) { Z[i] = (cd*)(q0 + (2 * i) * hb); Q[i] = (cd*)(q0 + (2 * i + 1) * hb); }
+    cd* rr = (cd*)(q0 + 2 * FGCR_M * hb);  // residual
+    if (!ctx->dots) HIPCHK(hipMalloc(&ctx->dots, sizeof(double) * 32));
+    ensure_partials_mr(ctx);
+    double* dh = ctx->hscal + BATCH_OFF;  // host copies of the dots (batch area unused here)
+    CgOut o;
+    *fell_back = false;
+    HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
+    HIPCHK(hipMemcpyAsync(rr, W.bh, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    const double b2 = norm2_half(ctx, W.bh);
+    if (b2 == 0.0) { o.converged = true; return o; }
+    double r2 = b2, best = b2, mark = b2;
+    double qq[FGCR_M];
+    int since = 0;
+    auto dots = [&](const cd* const* v, int nv, const cd* y) {
+        HIPCHK(launch_mdot(v, nv, y, nh, ctx->partials_mr, ctx->pstride, ctx->dots, ctx->st));
+        HIPCHK(hipMemcpyAsync(dh, ctx->dots, sizeof(double) * 2 * nv, hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+    };
+    while (o.iters < maxit) {
+        const int j = o.iters % FGCR_M;  // slot of the new direction (overwrites the oldest)
+        // z = N(Dhat^dag r), q = Dhat z
+        schur_dag64(ctx, W, Ad, rr, W.p);
+        cnn_apply_half(ctx, W.p, Z[j]);
+        schur64(ctx, W, Ai, Ad, Z[j], Q[j]);
+        o.applies += 2;
+        const cd* ko[FGCR_M];  // kept directions other than slot j
+        const cd* kz[FGCR_M];
+        int kept[FGCR_M], nk = 0;
+        for (int i = 0; i < std::min(o.iters, FGCR_M); i++)
+            if (i != j) { kept[nk] = i; ko[nk] = Q[i]; kz[nk] = Z[i]; nk++; }
+        if (nk > 0) {  // q -= sum_i <q_i, q>/|q_i|^2 q_i, same combination on z
+            dots(ko, nk, Q[j]);
+            double cr[FGCR_M], ci[FGCR_M];
+            for (int i = 0; i < nk; i++) { cr[i] = -dh[2 * i] / qq[kept[i]]; ci[i] = -dh[2 * i + 1] / qq[kept[i]]; }
+            HIPCHK(launch_maxpy(ko, cr, ci, nk, Q[j], nh, ctx->st));
+            HIPCHK(launch_maxpy(kz, cr, ci, nk, Z[j], nh, ctx->st));
+        }
+        const cd* qr[2] = {Q[j], Q[j]};
+        const cd* qv[1] = {Q[j]};
+        dots(qv, 1, Q[j]);
+        qq[j] = dh[0];
+        dots(qr, 1, rr);
+        const double ar = dh[0] / qq[j], ai = dh[1] / qq[j];
+        bool broke = !(qq[j] > 0) || !std::isfinite(ar) || !std::isfinite(ai);
+        if (!broke) {
+            const cd* zs[1] = {Z[j]};
+            const cd* qs[1] = {Q[j]};
+            double pr = ar, pi = ai, mr = -ar, mi = -ai;
+            HIPCHK(launch_maxpy(zs, &pr, &pi, 1, W.xcg, nh, ctx->st));
+            HIPCHK(launch_maxpy(qs, &mr, &mi, 1, rr, nh, ctx->st));
+            r2 = norm2_half(ctx, rr);
+            broke = !std::isfinite(r2);
+        }
+        o.iters++;
+        since++;
+        if (!broke && r2 <= tol_n * tol_n * b2) { o.converged = true; return o; }
+        if (r2 < best) best = r2;
+        if (since >= 20) {
+            if (best > 0.25 * mark) broke = true;  // less than 2x in norm over 20 iterations
+            mark = best;
+            since = 0;
+        }
+        if (broke) break;
+    }
+    // fall back to CG on the remaining defect: Dhat d = r, x += d
+    *fell_back = true;
+    HIPCHK(hipMemcpyAsync(W.bh, rr, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    HIPCHK(hipMemcpyAsync(Z[0], W.xcg, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    const double rel = std::sqrt(std::max(r2, 1e-300) / b2);
+    CgOut c = cg64(ctx, W, mp, mm, std::min(0.5, tol_n / rel), maxit - o.iters, auto_check_every_n(ctx));
+    HIPCHK(launch_axpby<double>(1.0, Z[0], 1.0, W.xcg, nh, nullptr, ctx->st));
+    o.iters += c.iters;
+    o.applies += c.applies;
+    o.converged = c.converged;
+    return o;
+}
+
 // ------------------------------------------------------------------ 5D solve D_T x = c
 struct SolveOut {
-    int iters = 0, applies = 0, restarts = 0, updates = 0;
+    int iters = 0, applies = 0, restarts = 0, updates = 0, fell_back = 0;
     double relres = 0;
     bool ok = false;
 };
@@ -443,7 +692,7 @@ double norm2_64(eofa_ctx* ctx, const Vec2& v) {
 
 // Even-odd solve of D_T d = rhs (rhs = W.res), result added to W.x.
 CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
-                   const eofa_solve_params& P, int* updates) {
+                   const eofa_solve_params& P, int* updates, int* fell_back) {
     const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
     // u_e = A^{-1} res_e ; bh = A^{-1} (res_o + 1/2 H_oe u_e)
     HIPCHK(launch_site<double>(ctx->Ns, false, W.res.h[0], W.u, Ai, ctx->g.Vh, ctx->st));
@@ -452,8 +701,16 @@ CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double 
         a.in = W.u; a.out = W.bh; a.aux = W.res.h[1]; a.caux = 1.0; a.cz = 0.5; a.opA = Ai;
         hop<double>(ctx, false, HM_SITE, false, a);
     }
-    CgOut o = (P.prec == EOFA_FP64) ? cg64(ctx, W, mp, mm, tol_n, maxit, check_every)
-                                    : cg_mixed(ctx, W, mp, mm, tol_n, maxit, check_every, P.reliable_delta, updates);
+    CgOut o;
+    if (P.pc == EOFA_PC_LEARNED) {
+        bool fb = false;
+        o = fgcr(ctx, W, mp, mm, tol_n, maxit, P, &fb);
+        if (fb && fell_back) *fell_back = 1;
+    } else if (P.prec == EOFA_FP64) {
+        o = cg64(ctx, W, mp, mm, tol_n, maxit, check_every);
+    } else {
+        o = cg_mixed(ctx, W, mp, mm, tol_n, maxit, check_every, P.reliable_delta, updates);
+    }
     // d_e = A^{-1} (res_e + 1/2 H_eo d_o) -> u ; x += d
     {
         auto a = hop_args<double>(ctx, 0);
@@ -489,7 +746,8 @@ void refine(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_sol
         if (attempt > 0) so.restarts++;
         // inner target on the normal residual, relative to the current defect
         double tol_n = std::max(0.25 * P.tol / rel, 1e-15);
-        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce, P, &so.updates);
+        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce, P, &so.updates,
+                               &so.fell_back);
         so.iters += o.iters;
         so.applies += o.applies;
         double r2 = residual64(ctx, W, mp, mm);
@@ -525,7 +783,7 @@ struct Sys {
 };
 
 void carve_batch(eofa_ctx* ctx, const eofa_solve_params& P, std::vector<Sys>& sys) {
-    char* q = ctx->ws + work64_bytes(ctx) + (P.prec != EOFA_FP64 ? work32_bytes(ctx) : 0);
+    char* q = ctx->ws + base_bytes(ctx, &P);
     const size_t h64 = align_up(ctx->nh * sizeof(cd));
     const size_t hk = align_up(ctx->nh * (P.prec != EOFA_FP64 ? sizeof(cpx<float>) : sizeof(cd)));
     for (Sys& y : sys) {
@@ -536,13 +794,6 @@ void carve_batch(eofa_ctx* ctx, const eofa_solve_params& P, std::vector<Sys>& sy
     }
 }
 
-void ensure_partials_mr(eofa_ctx* ctx) {
-    const int need = (int)(((size_t)ctx->g.Vh * ctx->Ns + 255) / 256) + 1;
-    if (ctx->partials_mr && ctx->pstride >= need) return;
-    if (ctx->partials_mr) HIPCHK(hipFree(ctx->partials_mr));
-    HIPCHK(hipMalloc(&ctx->partials_mr, sizeof(double) * (size_t)need * NRMAX));
-    ctx->pstride = need;
-}
 
 double* sys_scal(eofa_ctx* ctx, int r) { return ctx->scal + BATCH_OFF + r * SC_N; }
 
@@ -683,7 +934,10 @@ void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
 
 SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
     REQUIRE(P.prec == EOFA_FP64 || P.prec == EOFA_MIXED_FP32, EOFA_ENOTIMPL, "EOFA_MIXED_FP16 is not available in this build");
-    REQUIRE(P.pc == EOFA_PC_NONE, EOFA_ENOTIMPL, "learned preconditioner not available in this build");
+    if (P.pc == EOFA_PC_LEARNED) {
+        REQUIRE(ctx->cnn.ready, EOFA_ESTATE, "learned preconditioner: no weights (eofa_cnn_init or eofa_set_precond)");
+        REQUIRE(ctx->Ns % 8 == 0, EOFA_EINVAL, "learned preconditioner needs Ns % 8 == 0");
+    }
     return solve_dt_fp64(ctx, W, mp, mm, P);
 }
 
@@ -692,7 +946,7 @@ void fill_info(eofa_solve_info* info, const SolveOut& so, double secs) {
     info->iters = so.iters;
     info->op_applies = so.applies;
     info->reliable_updates = so.restarts + 1 + so.updates;
-    info->fell_back = 0;
+    info->fell_back = so.fell_back;
     info->true_rel_resid = so.relres;
     info->seconds = secs;
 }
@@ -1025,7 +1279,8 @@ eofa_status eofa_create(eofa_ctx** out, const int dims[4], int Ns, double m0, co
         ctx->st = (hipStream_t)hip_stream;
         ctx->g = Geom{dims[0], dims[1], dims[2], dims[3], dims[0] / 2, (int)(V / 2)};
         ctx->nh = (size_t)(V / 2) * 12 * Ns;
-        const size_t maxblk = (ctx->nh + 255) / 256 + 1024;
+        // one partial per block: hop kernels use <= nh / 256 blocks, grid-stride reductions <= 4096
+        const size_t maxblk = (ctx->nh + 255) / 256 + 4096;
         HIPCHK(hipMalloc(&ctx->partials, sizeof(double) * maxblk));
         HIPCHK(hipMalloc(&ctx->scal, sizeof(double) * SCAL_TOTAL));
         HIPCHK(hipMemset(ctx->scal, 0, sizeof(double) * SCAL_TOTAL));
@@ -1255,10 +1510,175 @@ eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[7]) {
     });
 }
 
-eofa_status eofa_set_precond(eofa_ctx* ctx, const void* weights_dev, size_t bytes) {
+eofa_status eofa_set_precond(eofa_ctx* ctx, const float* params_host, size_t count, int relu) {
     return guarded(ctx, [&]() -> eofa_status {
-        (void)weights_dev; (void)bytes;
-        REQUIRE(false, EOFA_ENOTIMPL, "learned preconditioner not available in this build");
+        REQUIRE(params_host && count == (size_t)CNN_NPARAM, EOFA_EINVAL,
+                "eofa_set_precond expects " + std::to_string(CNN_NPARAM) + " FP32 parameters");
+        REQUIRE(ctx->Ns % 8 == 0, EOFA_EINVAL, "learned preconditioner needs Ns % 8 == 0");
+        for (size_t i = 0; i < count; i++) REQUIRE(std::isfinite(params_host[i]), EOFA_EINVAL, "non-finite parameter");
+        cnn_alloc(ctx);
+        ctx->cnn.relu = relu ? 1 : 0;
+        HIPCHK(hipMemcpy(ctx->cnn.P, params_host, sizeof(float) * count, hipMemcpyHostToDevice));
+        HIPCHK(hipMemset(ctx->cnn.M, 0, sizeof(float) * count));
+        HIPCHK(hipMemset(ctx->cnn.V, 0, sizeof(float) * count));
+        ctx->cnn.step = 0;
+        cnn_refresh(ctx);
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        ctx->cnn.ready = true;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_cnn_init(eofa_ctx* ctx, unsigned long long seed, int relu) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->Ns % 8 == 0, EOFA_EINVAL, "learned preconditioner needs Ns % 8 == 0");
+        std::vector<float> h(CNN_NPARAM, 0.0f);
+        uint64_t x = seed * 0x9E3779B97F4A7C15ull + 0x2545F4914F6CDD1Dull;
+        auto u01 = [&]() {  // xorshift64*, 53-bit uniform in (0, 1)
+            x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
+            return ((double)((x * 0x2545F4914F6CDD1Dull) >> 11) + 0.5) / 9007199254740992.0;
+        };
+        for (int l = 0; l < CNN_LAYERS; l++) {
+            const double sd = std::sqrt((relu ? 2.0 : 1.0) / (81.0 * CNN_CIN[l]));
+            for (int tap = 0; tap < 81; tap++)
+                for (int n = 0; n < CNN_COUT[l]; n++)
+                    for (int k = 0; k < CNN_CIN[l]; k++) {
+                        const double g = std::sqrt(-2.0 * std::log(u01())) * std::cos(6.283185307179586 * u01());
+                        h[(size_t)l * CNN_LSZ + (size_t)tap * 1024 + n * 32 + k] = (float)(sd * g);
+                    }
+        }
+        cnn_alloc(ctx);
+        ctx->cnn.relu = relu ? 1 : 0;
+        HIPCHK(hipMemcpy(ctx->cnn.P, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemset(ctx->cnn.M, 0, sizeof(float) * h.size()));
+        HIPCHK(hipMemset(ctx->cnn.V, 0, sizeof(float) * h.size()));
+        ctx->cnn.step = 0;
+        cnn_refresh(ctx);
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        ctx->cnn.ready = true;
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_cnn_params(eofa_ctx* ctx, float* params_host, size_t count) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->cnn.ready, EOFA_ESTATE, "no network");
+        REQUIRE(params_host && count == (size_t)CNN_NPARAM, EOFA_EINVAL, "bad parameter buffer");
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        HIPCHK(hipMemcpy(params_host, ctx->cnn.P, sizeof(float) * count, hipMemcpyDeviceToHost));
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_cnn_apply(eofa_ctx* ctx, const void* in5, void* out5) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->cnn.ready, EOFA_ESTATE, "no network");
+        REQUIRE(in5 && out5 && in5 != out5, EOFA_EINVAL, "bad field pointers");
+        eofa_solve_params P{1e-10, 1, EOFA_FP64, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        Work64 W = carve64(ctx);
+        HIPCHK(launch_pack5<double>((const cd*)in5, W.r, ctx->g, 1, ctx->Ns, 0, ctx->st));
+        cnn_apply_half(ctx, W.r, W.p);
+        HIPCHK(hipMemsetAsync(W.u, 0, ctx->nh * sizeof(cd), ctx->st));
+        HIPCHK(launch_unpack5<double>(W.u, (cd*)out5, ctx->g, 0, ctx->Ns, 0, ctx->st));
+        HIPCHK(launch_unpack5<double>(W.p, (cd*)out5, ctx->g, 1, ctx->Ns, 0, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        return EOFA_OK;
+    });
+}
+
+// gradient (grad_host, may be NULL) and/or an Adam step (lr > 0) for one pair of canonical 5D fields
+eofa_status eofa_cnn_train_step(eofa_ctx* ctx, const void* rho5, const void* e5, double lr, double* loss,
+                                float* grad_host) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->cnn.ready, EOFA_ESTATE, "no network");
+        REQUIRE(rho5 && e5, EOFA_EINVAL, "bad field pointers");
+        eofa_solve_params P{1e-10, 1, EOFA_FP64, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        Work64 W = carve64(ctx);
+        HIPCHK(launch_pack5<double>((const cd*)rho5, W.r, ctx->g, 1, ctx->Ns, 0, ctx->st));
+        HIPCHK(launch_pack5<double>((const cd*)e5, W.p, ctx->g, 1, ctx->Ns, 0, ctx->st));
+        const double L = cnn_grad(ctx, W.r, W.p);
+        if (loss) *loss = L;
+        auto& c = ctx->cnn;
+        if (grad_host) {
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            HIPCHK(hipMemcpy(grad_host, c.G, sizeof(float) * CNN_NPARAM, hipMemcpyDeviceToHost));
+        }
+        if (lr > 0) {
+            c.step++;
+            const float b1 = 0.9f, b2 = 0.999f;
+            const float c1 = 1.0f - std::pow(b1, (float)c.step), c2 = 1.0f - std::pow(b2, (float)c.step);
+            HIPCHK(cnn_adam(c.P, c.G, c.M, c.V, CNN_NPARAM, (float)lr, b1, b2, 1e-8f, c1, c2, 1.0f, ctx->st));
+            cnn_refresh(ctx);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+        }
+        return EOFA_OK;
+    });
+}
+
+// Training pairs from one CG solve of Dhat(mp, mm) x = b with a Gaussian b on the odd sites (seeded):
+// snapshots x_k at k = 2, 4, 8, ...; after convergence e_k = x* - x_k and rho_k = Dhat^dag Dhat e_k,
+// written as canonical 5D fields (odd sites; even sites zero).  *made = number of pairs written (<= n).
+eofa_status eofa_training_pairs(eofa_ctx* ctx, double mp, double mm, unsigned long long seed, int n,
+                                void* const* rho5, void* const* e5, int* made) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+        REQUIRE(n >= 1 && n <= 16 && rho5 && e5 && made, EOFA_EINVAL, "bad arguments");
+        eofa_solve_params P{1e-10, 1, EOFA_FP64, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        Work64 W = carve64(ctx);
+        const size_t nh = ctx->nh;
+        {   // Gaussian source on the odd sites
+            std::vector<cd> h(nh);
+            uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+            auto u01 = [&]() {
+                x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
+                return ((double)((x * 0x2545F4914F6CDD1Dull) >> 11) + 0.5) / 9007199254740992.0;
+            };
+            for (size_t i = 0; i < nh; i++) {
+                const double r = std::sqrt(-std::log(u01())), t = 6.283185307179586 * u01();
+                h[i] = {r * std::cos(t), r * std::sin(t)};
+            }
+            HIPCHK(hipMemcpy(W.bh, h.data(), nh * sizeof(cd), hipMemcpyHostToDevice));
+        }
+        const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+        const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+        // CG as in cg64, with snapshots of x into the odd sites of e5[i]
+        HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
+        HIPCHK(launch_scal_set(ctx->scal, SC_TOL2, 1e-24, -1, 0, -1, 0, ctx->st));
+        double rr = normal_residual64(ctx, W, W.xcg, W.bh, Ai, Ad);
+        HIPCHK(hipMemcpyAsync(W.p, W.r, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+        HIPCHK(launch_scal_set(ctx->scal, SC_RR, rr, SC_RR0, rr, SC_DONE, 0.0, ctx->st));
+        int k = 0, snap = 0, next = 2;
+        const int ce = auto_check_every_n(ctx);
+        while (k < 100000) {
+            cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
+            k++;
+            if (k == next && snap < n) {
+                HIPCHK(hipMemsetAsync(W.res.h[0], 0, nh * sizeof(cd), ctx->st));
+                HIPCHK(launch_unpack5<double>(W.res.h[0], (cd*)e5[snap], ctx->g, 0, ctx->Ns, 0, ctx->st));
+                HIPCHK(launch_unpack5<double>(W.xcg, (cd*)e5[snap], ctx->g, 1, ctx->Ns, 0, ctx->st));
+                snap++;
+                next *= 2;
+            }
+            if (k % ce == 0) {
+                sync_scal(ctx);
+                if (ctx->hscal[SC_DONE] != 0.0 || !std::isfinite(ctx->hscal[SC_RR])) break;
+            }
+        }
+        // e_i = x* - x_i ; rho_i = Dhat^dag Dhat e_i
+        for (int i = 0; i < snap; i++) {
+            HIPCHK(launch_pack5<double>((const cd*)e5[i], W.c.h[1], ctx->g, 1, ctx->Ns, 0, ctx->st));
+            HIPCHK(launch_axpby<double>(1.0, W.xcg, -1.0, W.c.h[1], nh, nullptr, ctx->st));
+            schur64(ctx, W, Ai, Ad, W.c.h[1], W.w);
+            schur_dag64(ctx, W, Ad, W.w, W.p);
+            HIPCHK(launch_unpack5<double>(W.c.h[1], (cd*)e5[i], ctx->g, 1, ctx->Ns, 0, ctx->st));
+            HIPCHK(launch_unpack5<double>(W.res.h[0], (cd*)rho5[i], ctx->g, 0, ctx->Ns, 0, ctx->st));
+            HIPCHK(launch_unpack5<double>(W.p, (cd*)rho5[i], ctx->g, 1, ctx->Ns, 0, ctx->st));
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        *made = snap;
         return EOFA_OK;
     });
 }
@@ -1275,6 +1695,13 @@ void eofa_destroy(eofa_ctx* ctx) {
     if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->partials_mr) (void)hipFree(ctx->partials_mr);
+    {
+        auto& c = ctx->cnn;
+        void* ptrs[] = {c.P, c.G, c.M, c.V, c.Wb, c.Wt, c.X0, c.A[0], c.A[1], c.A[2], c.dYb, c.XT, c.dYT,
+                        c.Y, c.T, c.dY, c.dA, c.part, ctx->dots};
+        for (void* q : ptrs)
+            if (q) (void)hipFree(q);
+    }
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (auto& e : ctx->ev_pool) {

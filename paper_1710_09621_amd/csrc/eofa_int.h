@@ -74,6 +74,13 @@ template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>
 template <typename R> hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red,
                                               hipStream_t st);
 template <typename R> hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st);
+// out[2i] + i out[2i+1] = <v_i, y> (complex, FP64, deterministic), i < nv <= 9; partials >= 2 nv x pstride
+hipError_t launch_mdot(const cd* const* v, int nv, const cd* y, size_t n, double* partials, int pstride, double* out,
+                       hipStream_t st);
+// y += sum_i (cr_i + i ci_i) v_i, nv <= 9
+hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, int nv, cd* y, size_t n, hipStream_t st);
+// one-block finish of a reduction whose nblocks partials are in r.partials
+hipError_t launch_finish(const Red& r, unsigned nblocks, hipStream_t st);
 // dst[i] = host_vals[i], i < n <= 64 (values travel as kernel arguments: the host array may die at once)
 hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream_t st);
 // sets S[s_i] = v_i for the slots s_i >= 0 (stream-ordered, no host buffer)

@@ -453,6 +453,64 @@ __global__ __launch_bounds__(256) void k_accum_lo(cd* __restrict__ xhi, const cp
     }
 }
 
+// complex dot products <v_i, y> = sum conj(v_i) y for i < nv (nv <= 9): partials[2i][blk] (re), [2i+1][blk] (im)
+struct DotArgs {
+    const cd* v[9];
+    int nv;
+};
+__global__ __launch_bounds__(256) void k_mdot(const DotArgs a, const cd* __restrict__ y, size_t n, double* partials,
+                                              int pstride) {
+    double re[9], im[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) { re[i] = 0; im[i] = 0; }
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+        const cd yy = y[k];
+#pragma unroll
+        for (int i = 0; i < 9; i++)
+            if (i < a.nv) {
+                const cd vv = a.v[i][k];
+                re[i] = fma(vv.x, yy.x, fma(vv.y, yy.y, re[i]));
+                im[i] = fma(vv.x, yy.y, fma(-vv.y, yy.x, im[i]));
+            }
+    }
+    __shared__ double lds[4];
+    for (int i = 0; i < a.nv; i++) {
+        const double r = block_sum256(re[i], lds);
+        const double m = block_sum256(im[i], lds);
+        if (threadIdx.x == 0) {
+            partials[(size_t)(2 * i) * pstride + blockIdx.x] = r;
+            partials[(size_t)(2 * i + 1) * pstride + blockIdx.x] = m;
+        }
+    }
+}
+
+// y += sum_i c_i v_i (complex c_i, nv <= 9)
+struct AxpyArgs {
+    const cd* v[9];
+    double cr[9], ci[9];
+    int nv;
+};
+__global__ __launch_bounds__(256) void k_maxpy(const AxpyArgs a, cd* __restrict__ y, size_t n) {
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (size_t)gridDim.x * 256) {
+        cd yy = y[k];
+        for (int i = 0; i < a.nv; i++) {
+            const cd vv = a.v[i][k];
+            yy.x = fma(a.cr[i], vv.x, fma(-a.ci[i], vv.y, yy.x));
+            yy.y = fma(a.cr[i], vv.y, fma(a.ci[i], vv.x, yy.y));
+        }
+        y[k] = yy;
+    }
+}
+
+__global__ void k_finish_many(const double* __restrict__ partials, int pstride, unsigned n, double* out) {
+    // block b sums partials[b * pstride .. + n) into out[b]
+    __shared__ double lds[4];
+    double s = 0.0;
+    for (unsigned i = threadIdx.x; i < n; i += 256) s += partials[(size_t)blockIdx.x * pstride + i];
+    s = block_sum256(s, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 // ===================================================================== boundary kernels
 // canonical index of (s, lex site, j): ((s * V + lex) * 12 + j)
 __device__ __forceinline__ void cb_to_lex(const Geom& g, int cb, int par, int& lex) {
@@ -596,9 +654,37 @@ static inline void finish(const Red& r, unsigned nblocks, hipStream_t st) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, r.partials, nblocks, r.scal, r.slot, r.epi);
 }
 
+hipError_t launch_finish(const Red& r, unsigned nblocks, hipStream_t st) {
+    finish(r, nblocks, st);
+    return hipGetLastError();
+}
+
 static inline int nblk(size_t n) {
     size_t b = (n + 255) / 256;
     return (int)(b > 4096 ? 4096 : b);
+}
+
+hipError_t launch_mdot(const cd* const* v, int nv, const cd* y, size_t n, double* partials, int pstride, double* out,
+                       hipStream_t st) {
+    if (nv < 1 || nv > 9) return hipErrorInvalidValue;
+    DotArgs a{};
+    for (int i = 0; i < nv; i++) a.v[i] = v[i];
+    a.nv = nv;
+    const int grid = nblk(n) > 1024 ? 1024 : nblk(n);
+    if (grid > pstride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mdot, dim3(grid), dim3(256), 0, st, a, y, n, partials, pstride);
+    hipLaunchKernelGGL(k_finish_many, dim3(2 * nv), dim3(256), 0, st, partials, pstride, (unsigned)grid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, int nv, cd* y, size_t n, hipStream_t st) {
+    if (nv < 0 || nv > 9) return hipErrorInvalidValue;
+    if (nv == 0) return hipSuccess;
+    AxpyArgs a{};
+    for (int i = 0; i < nv; i++) { a.v[i] = v[i]; a.cr[i] = cr[i]; a.ci[i] = ci[i]; }
+    a.nv = nv;
+    hipLaunchKernelGGL(k_maxpy, dim3(nblk(n)), dim3(256), 0, st, a, y, n);
+    return hipGetLastError();
 }
 
 #define NS_SWITCH(NSV, ...)                                            \

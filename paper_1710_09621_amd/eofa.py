@@ -22,6 +22,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
 PC_NONE, PC_LEARNED = 0, 1
+CNN_NPARAM = 4 * (81 * 32 * 32 + 32)
 OPS = dict(DW=0, HOP=1, DT=2, DT_DAG=3, HT=4, AT_INV=5, SCHUR=6, SCHUR_DAG=7, SCHUR_NORMAL=8)
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "ESTATE", -6: "ENOTIMPL"}
 
@@ -76,7 +77,12 @@ def load():
         "eofa_apply": [P, I, D, D, P, P, I],
         "eofa_hop_timing": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)],
         "eofa_hop_timing_reset": [P],
-        "eofa_set_precond": [P, P, Z],
+        "eofa_set_precond": [P, C.POINTER(C.c_float), Z, I],
+        "eofa_cnn_init": [P, C.c_ulonglong, I],
+        "eofa_cnn_params": [P, C.POINTER(C.c_float), Z],
+        "eofa_cnn_apply": [P, P, P],
+        "eofa_cnn_train_step": [P, P, P, D, C.POINTER(C.c_double), C.POINTER(C.c_float)],
+        "eofa_training_pairs": [P, D, D, C.c_ulonglong, I, PP, PP, C.POINTER(C.c_int)],
         "eofa_dslash_bench": [P, I, I, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "eofa_autotune": [P, I, I, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "eofa_set_schedule": [P, I, C.POINTER(C.c_int)],
@@ -98,7 +104,9 @@ def exported_symbols():
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
                         "eofa_chiral_action", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
-                        "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_hop_timing", "eofa_hop_timing_reset", "eofa_set_precond",
+                        "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
+                        "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
+                        "eofa_hop_timing", "eofa_hop_timing_reset", "eofa_set_precond",
                         "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
 
 
@@ -301,6 +309,49 @@ class Context:
         st = self.lib.eofa_hinv_batch(self.h, n, mlo, mhi, pin, pout, S, C.byref(p), info)
         self._check(st, "hinv_batch")
         return [Result(outs[j], S[j], [info[2 * j].as_dict(), info[2 * j + 1].as_dict()]) for j in range(n)]
+
+    # ---- learned preconditioner
+    def cnn_init(self, seed=0, relu=False):
+        self._check(self.lib.eofa_cnn_init(self.h, int(seed), int(bool(relu))), "cnn_init")
+
+    def set_precond(self, params_f32, relu=False):
+        w = np.ascontiguousarray(np.asarray(params_f32, dtype=np.float32).reshape(-1))
+        self._check(self.lib.eofa_set_precond(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size,
+                                              int(bool(relu))), "set_precond")
+
+    def cnn_params(self):
+        w = np.empty(CNN_NPARAM, dtype=np.float32)
+        self._check(self.lib.eofa_cnn_params(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size), "cnn_params")
+        return w
+
+    def cnn_apply(self, x5):
+        x5 = self._c128(x5, self.shape5)
+        out = self.torch.empty_like(x5)
+        self._prep_ws(params())
+        self._check(self.lib.eofa_cnn_apply(self.h, _ptr(x5), _ptr(out)), "cnn_apply")
+        return out
+
+    def cnn_train_step(self, rho5, e5, lr=1e-3, want_grad=False):
+        rho5 = self._c128(rho5, self.shape5)
+        e5 = self._c128(e5, self.shape5)
+        self._prep_ws(params())
+        loss = C.c_double()
+        g = np.empty(CNN_NPARAM, dtype=np.float32) if want_grad else None
+        gp = g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None
+        self._check(self.lib.eofa_cnn_train_step(self.h, _ptr(rho5), _ptr(e5), float(lr), C.byref(loss), gp),
+                    "cnn_train_step")
+        return (loss.value, g) if want_grad else loss.value
+
+    def training_pairs(self, mp, mm, seed, n=8):
+        self._prep_ws(params())
+        rho = [self.torch.empty(self.shape5, dtype=self.torch.complex128, device=self.device) for _ in range(n)]
+        e = [self.torch.empty(self.shape5, dtype=self.torch.complex128, device=self.device) for _ in range(n)]
+        pr = (C.c_void_p * n)(*[t.data_ptr() for t in rho])
+        pe = (C.c_void_p * n)(*[t.data_ptr() for t in e])
+        made = C.c_int()
+        self._check(self.lib.eofa_training_pairs(self.h, float(mp), float(mm), int(seed), n, pr, pe, C.byref(made)),
+                    "training_pairs")
+        return list(zip(rho[:made.value], e[:made.value]))
 
     def hop_timing(self, enable=True):
         ms, n, b = C.c_double(), C.c_long(), C.c_double()

@@ -111,6 +111,21 @@ def optimal_omega(Ns: int, lmin: float = 0.05, lmax: float = 6.2) -> np.ndarray:
     return np.concatenate([w, w[::-1]])
 
 
+def cnn_params(seed, scale=1.0):
+    """Seeded parameters of the 4-layer preconditioner network (channels 24, 32, 32, 32, 24, 81 taps):
+    per layer N(0, scale^2 / (81 cin)) weights [81][32 out][32 in], N(0, (0.1 scale)^2) biases [32],
+    zero in the padding channels.  Returns float32 [4 * (81 * 1024 + 32)]."""
+    cin, cout = (24, 32, 32, 32), (32, 32, 32, 24)
+    wsz, lsz = 81 * 32 * 32, 81 * 32 * 32 + 32
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = np.zeros(4 * lsz)
+    for l in range(4):
+        W = p[l * lsz: l * lsz + wsz].reshape(81, 32, 32)
+        W[:, :cout[l], :cin[l]] = rng.normal(0, scale / np.sqrt(81 * cin[l]), (81, cout[l], cin[l]))
+        p[l * lsz + wsz: l * lsz + wsz + cout[l]] = rng.normal(0, 0.1 * scale, cout[l])
+    return p.astype(np.float32)
+
+
 # The five synthetic workloads (lattice dims are (Lx, Ly, Lz, Lt)).
 CONFIGS = {
     1: dict(dims=(4, 4, 4, 4), Ns=8, eps=0.3, seed=1, masses=(0.05, 1.0), nsrc=1),
