@@ -45,12 +45,34 @@ def cpu_baseline(U, dims, Ns, omega, budget_s=12.0):
         lat.hop(psi)
         n += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 64:
+        if el >= budget_s or n >= 512:
             break
     gbs = per_site * V * n / el / 1e9
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"oracle FP64 Wilson hop on the full 4D lattice {dims}, one s-slice per application, "
                       f"{n} applications in {el:.1f} s; bytes per 5D output site as for the GPU hop ({per_site:.0f} B)"}
+
+
+def measured_traffic(path, dims, Ns):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or None
+    when there is none for this lattice or the kernel sources changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        h = hashlib.sha1()
+        for p in t["source_files"]:
+            with open(os.path.join(ROOT, p), "rb") as f:
+                h.update(f.read())
+        lat = "x".join(str(d) for d in dims)
+        if h.hexdigest() != t["source_sha1"] or t["lattice"] != lat or t["Ns"] != Ns:
+            log("counter summary is stale (kernel sources or lattice changed): traffic = null")
+            return None
+        return round(float(t["bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -164,13 +186,7 @@ def main():
         f"avg {per_launch_ms:.4f} ms -> {hop_gbs:.1f} GB/s; iters {iters} / {iters_t}; max resid {max(resid):.2e}; "
         f"max |dS|/S {dS:.1e}")
 
-    traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            with open(args.traffic) as f:
-                traffic = json.load(f).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic(args.traffic, dims, Ns)
 
     Vh = int(np.prod(dims)) // 2
     alg_bytes = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)

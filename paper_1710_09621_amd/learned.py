@@ -52,7 +52,7 @@ def identity_init(seed, noise=0.05):
     return p.astype(np.float32)
 
 
-def train(ctx, fields, mp, mm, steps=400, lr=2e-3, lr_end=2e-4, seed=0, relu=False, n_cg=8, n_rand=4,
+def train(ctx, fields, mp, mm, steps=1000, lr=2e-4, lr_end=2e-5, seed=0, relu=False, n_cg=0, n_rand=8,
           steps_per_field=50, init="identity", log=None):
     """Train the network of ctx in place on pairs from the gauge fields (list of (seed, links)).
     init: "identity" (near-identity linear network) or "he" (random He-normal).  Returns the loss history."""
@@ -106,8 +106,10 @@ def evaluate(ctx, fields, mp, mm, tol=1e-10, nsrc=1, log=None):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--config", type=int, default=4)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--lr", type=float, default=2e-4)
+    ap.add_argument("--n-cg", type=int, default=0, help="pairs per field from CG iterates")
+    ap.add_argument("--n-rand", type=int, default=8, help="pairs per field from Gaussian errors")
     ap.add_argument("--relu", action="store_true")
     ap.add_argument("--save", default=None, help="write the trained parameters (float32 .npy)")
     ap.add_argument("--json", default=None, help="write the evaluation records")
@@ -120,7 +122,7 @@ def main(argv=None):
     train_f = [(s, IN.gauge_links(dims, eps, s)) for s in cfg["train_seeds"]]
     hold_f = [(s, IN.gauge_links(dims, eps, s)) for s in cfg["heldout_seeds"]]
     t0 = time.perf_counter()
-    hist = train(ctx, train_f, mp, mm, steps=a.steps, lr=a.lr, relu=a.relu, log=log)
+    hist = train(ctx, train_f, mp, mm, steps=a.steps, lr=a.lr, relu=a.relu, n_cg=a.n_cg, n_rand=a.n_rand, log=log)
     t_train = time.perf_counter() - t0
     recs = evaluate(ctx, hold_f, mp, mm, log=log)
     summary = dict(config=a.config, steps=a.steps, train_seconds=t_train, final_loss=float(np.mean(hist[-50:])),
