@@ -63,7 +63,8 @@ typedef struct {
     eofa_precision prec;   /* storage precision of the inner Krylov solver */
     eofa_precond pc;       /* EOFA_PC_LEARNED: flexible GCR with the learned preconditioner */
     double reliable_delta; /* mixed precision: reliable update when ||r|| drops by this factor (0: 0.1) */
-    int use_graph;         /* capture check_every iterations in a hipGraph and replay it */
+    int use_graph;         /* capture blocks of check_every CG iterations in a hipGraph (once per buffer
+                              set, cached in the context) and replay them; same arithmetic as eager */
     int check_every;       /* iterations between host convergence checks (0: automatic) */
 } eofa_solve_params;
 
@@ -159,6 +160,9 @@ eofa_status eofa_apply(eofa_ctx *ctx, int op, double m_plus, double m_minus, con
  * hop launch (adds a small overhead); eofa_hop_timing_reset clears the counters. */
 eofa_status eofa_hop_timing(eofa_ctx *ctx, int enable, double *ms, long *launches, double *bytes);
 eofa_status eofa_hop_timing_reset(eofa_ctx *ctx);
+
+/* Graph replays since the context was created and the number of instantiated graphs it holds. */
+eofa_status eofa_graph_stats(eofa_ctx *ctx, long *replays, int *cached);
 
 /* Diagnostic: nrep back-to-back launches of the fused even-odd hop with its A_T^{-1} epilogue
  * (u = A_T^{-1} H_eo p, alternating parities, masses 0.01) on workspace buffers, in EOFA_FP64 or

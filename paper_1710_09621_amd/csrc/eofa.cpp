@@ -69,6 +69,10 @@ struct eofa_ctx {
         long step = 0;
     } cnn;
     double* dots = nullptr;  // FGCR dot products (device)
+    // captured CG-iteration blocks (use_graph): key = every launch argument that can vary
+    hipStream_t cap_st = nullptr;
+    std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
+    long graph_replays = 0;
     // workgroup schedules of the hop kernels, per storage precision (0: FP64, 1: FP32); set by the autotuner
     Sched sched[2] = {{0, 0, 1, 1, 1, 1, 0}, {0, 0, 1, 1, 1, 1, 0}};
     double tuned_ms[2] = {0, 0};
@@ -272,6 +276,60 @@ void collect_timing(eofa_ctx* ctx) {
     ctx->ev_used = 0;
 }
 
+// Launch the work of body() (kernel launches on ctx->st only: no host synchronisation, copies or
+// memsets) as one replay of a captured graph.  The capture runs once per key on a private stream
+// (the caller's stream may be the legacy default stream, which cannot be captured) and the
+// instantiated graph is replayed on ctx->st.  Kernel arguments are captured by value, so the key
+// holds every pointer and parameter the launches take.
+template <typename F> void graph_run(eofa_ctx* ctx, std::vector<uintptr_t> key, F&& body) {
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 64) {
+            for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+            ctx->graphs.clear();
+        }
+        if (!ctx->cap_st) HIPCHK(hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
+        hipStream_t user = ctx->st;
+        const bool timing = ctx->timing;
+        ctx->st = ctx->cap_st;
+        ctx->timing = false;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            try {
+                body();
+            } catch (...) {
+                (void)hipStreamEndCapture(ctx->cap_st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                ctx->st = user;
+                ctx->timing = timing;
+                throw;
+            }
+            e = hipStreamEndCapture(ctx->cap_st, &g);
+        }
+        ctx->st = user;
+        ctx->timing = timing;
+        HIPCHK(e);
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        it = ctx->graphs.emplace(std::move(key), ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, ctx->st));
+    ctx->graph_replays++;
+}
+
+template <typename R> std::vector<uintptr_t> graph_key(const eofa_ctx* ctx, int kind, int n,
+                                                       std::initializer_list<const void*> ptrs) {
+    std::vector<uintptr_t> k{(uintptr_t)kind, (uintptr_t)n, sizeof(R), (uintptr_t)ctx->scal,
+                             (uintptr_t)ctx->partials, (uintptr_t)ctx->partials_mr, (uintptr_t)ctx->pstride};
+    const Sched& sc = ctx->sched[sizeof(R) == 8 ? 0 : 1];
+    for (int v : {sc.mode, sc.xcd, sc.ty, sc.tz, sc.tt, sc.nyb, sc.ord}) k.push_back((uintptr_t)v);
+    for (const void* p : ptrs) k.push_back((uintptr_t)p);
+    return k;
+}
+
 // One CG iteration on Dhat^dag Dhat in storage/arithmetic type R (the four fused hops + BLAS).
 template <typename R>
 void cg_iteration(eofa_ctx* ctx, cpx<R>* x, cpx<R>* r, cpx<R>* p, cpx<R>* u, cpx<R>* w, cpx<R>* wt, cpx<R>* at,
@@ -309,7 +367,8 @@ struct CgOut {
 };
 
 // Solve Dhat x = bh (odd sites) to |r_normal| <= tol_n |r_normal,0|; x starts at zero.
-CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every) {
+CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
+           bool graph = false) {
     const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
     const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
     const size_t nh = ctx->nh;
@@ -337,9 +396,19 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
     while (o.iters < maxit) {
         // u = A^{-1} H_eo p ; w = Dhat p, wt = A^{-dag} w, |w|^2 -> alpha ; at = A^{-dag} g5 H_eo g5 wt ;
         // r -= alpha (w - g5 H_oe g5 at / 4), |r|^2 -> beta ; x += alpha p, p = r + beta p
-        cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
-        o.iters++;
-        o.applies += 2;
+        if (graph && o.iters % check_every == 0 && o.iters + check_every <= maxit) {
+            graph_run(ctx, graph_key<double>(ctx, 1, check_every, {W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad}),
+                      [&] {
+                          for (int k = 0; k < check_every; k++)
+                              cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
+                      });
+            o.iters += check_every;
+            o.applies += 2 * check_every;
+        } else {
+            cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
+            o.iters++;
+            o.applies += 2;
+        }
         if (o.iters % check_every == 0 || o.iters == maxit) {
             sync_scal(ctx);
             double rr = ctx->hscal[SC_RR];
@@ -411,7 +480,7 @@ double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const cd* 
 // accumulation and FP64 residual replacement whenever |r| has dropped by delta since the
 // last replacement.  Solves Dhat W.xcg = W.bh to |r_normal| <= tol_n |r_normal,0|.
 CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
-               double delta, int* updates) {
+               double delta, int* updates, bool graph = false) {
     const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
     const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
     const Work32 F = carve32(ctx);
@@ -434,10 +503,21 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
         HIPCHK(launch_scal_set(ctx->scal, SC_DONE, 0.0, -1, 0, -1, 0, ctx->st));
         int inner = 0;
         while (o.iters < maxit) {
-            cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
-            o.iters++;
-            inner++;
-            o.applies += 2;
+            if (graph && inner % check_every == 0 && o.iters + check_every <= maxit) {
+                graph_run(ctx, graph_key<float>(ctx, 2, check_every, {F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad}),
+                          [&] {
+                              for (int k = 0; k < check_every; k++)
+                                  cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
+                          });
+                o.iters += check_every;
+                inner += check_every;
+                o.applies += 2 * check_every;
+            } else {
+                cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
+                o.iters++;
+                inner++;
+                o.applies += 2;
+            }
             if (inner % check_every == 0) {
                 sync_scal(ctx);
                 if (!std::isfinite(ctx->hscal[SC_RR])) { ctx->err = "mixed CG breakdown"; return o; }
@@ -707,9 +787,9 @@ CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double 
         o = fgcr(ctx, W, mp, mm, tol_n, maxit, P, &fb);
         if (fb && fell_back) *fell_back = 1;
     } else if (P.prec == EOFA_FP64) {
-        o = cg64(ctx, W, mp, mm, tol_n, maxit, check_every);
+        o = cg64(ctx, W, mp, mm, tol_n, maxit, check_every, P.use_graph != 0);
     } else {
-        o = cg_mixed(ctx, W, mp, mm, tol_n, maxit, check_every, P.reliable_delta, updates);
+        o = cg_mixed(ctx, W, mp, mm, tol_n, maxit, check_every, P.reliable_delta, updates, P.use_graph != 0);
     }
     // d_e = A^{-1} (res_e + 1/2 H_eo d_o) -> u ; x += d
     {
@@ -856,7 +936,8 @@ template <typename R> void cg_iteration_mr(eofa_ctx* ctx, std::vector<Sys>& sys)
 // Batched CG on the systems' Schur normal equations to |r_normal| <= tol_n |r_normal,0| each.  With R = float
 // every system gets FP64 reliable updates (residual replacement) on its own schedule.
 template <typename R>
-void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_n, int maxit, int ce, double delta) {
+void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_n, int maxit, int ce, double delta,
+              bool graph = false) {
     const int nr = (int)sys.size();
     const bool mixed = sizeof(R) == 4;
     if (delta <= 0 || delta >= 1) delta = 0.1;
@@ -889,9 +970,23 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
         bool all = true;
         for (const Sys& y : sys) all &= y.conv;
         if (all) break;
-        cg_iteration_mr<R>(ctx, sys);
-        it++;
-        for (Sys& y : sys) if (!y.conv) y.iters++;
+        if (graph && it % ce == 0 && it + ce <= maxit) {
+            std::vector<uintptr_t> key = graph_key<R>(ctx, 3, ce, {});
+            for (const Sys& y : sys)
+                for (const void* q : {(const void*)y.Ai, (const void*)y.Ad, (const void*)y.x, (const void*)y.r,
+                                      (const void*)y.p, (const void*)y.u, (const void*)y.w, (const void*)y.wt,
+                                      (const void*)y.at})
+                    key.push_back((uintptr_t)q);
+            graph_run(ctx, std::move(key), [&] {
+                for (int k = 0; k < ce; k++) cg_iteration_mr<R>(ctx, sys);
+            });
+            it += ce;
+            for (Sys& y : sys) if (!y.conv) y.iters += ce;
+        } else {
+            cg_iteration_mr<R>(ctx, sys);
+            it++;
+            for (Sys& y : sys) if (!y.conv) y.iters++;
+        }
         if (it % ce && it < maxit) continue;
         sync_scal_batch(ctx, nr);
         for (int r = 0; r < nr; r++) {
@@ -1069,8 +1164,8 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
         }
         const double tol_n = 0.25 * P->tol;
         const int ce = auto_check_every(ctx, *P);
-        if (P->prec == EOFA_FP64) cg_batch<double>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta);
-        else cg_batch<float>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta);
+        if (P->prec == EOFA_FP64) cg_batch<double>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
+        else cg_batch<float>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
         HIPCHK(hipStreamSynchronize(ctx->st));
         const double tb = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / nr;
         for (int r = 0; r < nr; r++) {
@@ -1430,6 +1525,14 @@ eofa_status eofa_apply(eofa_ctx* ctx, int op, double m_plus, double m_minus, con
     });
 }
 
+eofa_status eofa_graph_stats(eofa_ctx* ctx, long* replays, int* cached) {
+    return guarded(ctx, [&]() -> eofa_status {
+        if (replays) *replays = ctx->graph_replays;
+        if (cached) *cached = (int)ctx->graphs.size();
+        return EOFA_OK;
+    });
+}
+
 eofa_status eofa_hop_timing(eofa_ctx* ctx, int enable, double* ms, long* launches, double* bytes) {
     return guarded(ctx, [&]() -> eofa_status {
         collect_timing(ctx);
@@ -1702,6 +1805,8 @@ void eofa_destroy(eofa_ctx* ctx) {
         for (void* q : ptrs)
             if (q) (void)hipFree(q);
     }
+    for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (ctx->cap_st) (void)hipStreamDestroy(ctx->cap_st);
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (auto& e : ctx->ev_pool) {

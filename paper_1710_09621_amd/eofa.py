@@ -78,6 +78,7 @@ def load():
         "eofa_hop_timing": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)],
         "eofa_hop_timing_reset": [P],
         "eofa_set_precond": [P, C.POINTER(C.c_float), Z, I],
+        "eofa_graph_stats": [P, C.POINTER(C.c_long), C.POINTER(C.c_int)],
         "eofa_cnn_init": [P, C.c_ulonglong, I],
         "eofa_cnn_params": [P, C.POINTER(C.c_float), Z],
         "eofa_cnn_apply": [P, P, P],
@@ -106,7 +107,7 @@ def exported_symbols():
                         "eofa_chiral_action", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
                         "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
-                        "eofa_hop_timing", "eofa_hop_timing_reset", "eofa_set_precond",
+                        "eofa_hop_timing", "eofa_graph_stats", "eofa_hop_timing_reset", "eofa_set_precond",
                         "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
 
 
@@ -309,6 +310,11 @@ class Context:
         st = self.lib.eofa_hinv_batch(self.h, n, mlo, mhi, pin, pout, S, C.byref(p), info)
         self._check(st, "hinv_batch")
         return [Result(outs[j], S[j], [info[2 * j].as_dict(), info[2 * j + 1].as_dict()]) for j in range(n)]
+
+    def graph_stats(self):
+        n, c = C.c_long(), C.c_int()
+        self._check(self.lib.eofa_graph_stats(self.h, C.byref(n), C.byref(c)), "graph_stats")
+        return {"replays": n.value, "cached": c.value}
 
     # ---- learned preconditioner
     def cnn_init(self, seed=0, relu=False):
