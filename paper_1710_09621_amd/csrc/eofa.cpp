@@ -156,10 +156,16 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 size_t work64_bytes(const eofa_ctx* ctx) { return 14 * align_up(ctx->nh * sizeof(cd)); }
 size_t work32_bytes(const eofa_ctx* ctx) { return 9 * align_up(ctx->nh * sizeof(cpx<float>)); }
 
-// per system of a multi-RHS batch: FP64 solution accumulator and Schur source, 7 Krylov vectors
+// per system of a multi-RHS batch: FP64 solution accumulator and Schur source, then the Krylov
+// vectors x, r (batch precision: FP64 or FP32) and p, u, w, wt, at (FP64, FP32 or FP16 columns)
+size_t batch_vec_bytes(const eofa_ctx* ctx, const eofa_solve_params* p, bool xr) {
+    const int prec = p ? p->prec : EOFA_FP64;
+    if (prec == EOFA_FP64) return align_up(ctx->nh * sizeof(cd));
+    if (prec == EOFA_MIXED_FP16 && !xr) return align_up(half_field_bytes_h(ctx->g, ctx->Ns));
+    return align_up(ctx->nh * sizeof(cpx<float>));
+}
 size_t batch_sys_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
-    const size_t kr = (p && p->prec != EOFA_FP64) ? sizeof(cpx<float>) : sizeof(cd);
-    return 2 * align_up(ctx->nh * sizeof(cd)) + 7 * align_up(ctx->nh * kr);
+    return 2 * align_up(ctx->nh * sizeof(cd)) + 2 * batch_vec_bytes(ctx, p, true) + 5 * batch_vec_bytes(ctx, p, false);
 }
 
 constexpr int FGCR_M = 8;  // directions kept before a restart
@@ -168,13 +174,16 @@ size_t fgcr_bytes(const eofa_ctx* ctx) { return (2 * FGCR_M + 1) * align_up(ctx-
 
 // workspace: FP64 set | FP32 set (mixed) | then either the FGCR directions or the batched systems
 size_t base_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
-    return work64_bytes(ctx) + ((p && p->prec != EOFA_FP64) ? work32_bytes(ctx) : 0);
+    return work64_bytes(ctx) + ((p && p->prec == EOFA_MIXED_FP32) ? work32_bytes(ctx) : 0);
 }
 
+// FP16 storage runs through the batch kernels, also for a single system
 size_t needed_bytes(const eofa_ctx* ctx, const eofa_solve_params* p, int nrhs = 1) {
     size_t extra = 0;
     if (p && p->pc == EOFA_PC_LEARNED) extra = fgcr_bytes(ctx);
-    if (nrhs > 1 && ctx->Ns >= 8) extra = std::max(extra, (size_t)std::min(nrhs, NRMAX) * batch_sys_bytes(ctx, p));
+    const bool fp16 = p && p->prec == EOFA_MIXED_FP16;
+    if ((nrhs > 1 || fp16) && ctx->Ns >= 8)
+        extra = std::max(extra, (size_t)std::min(nrhs, NRMAX) * batch_sys_bytes(ctx, p));
     return base_bytes(ctx, p) + extra;
 }
 
@@ -770,6 +779,9 @@ double norm2_64(eofa_ctx* ctx, const Vec2& v) {
     return ctx->hscal[SC_TMP + 2] + ctx->hscal[SC_TMP + 3];
 }
 
+CgOut cg_single_fp16(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int ce,
+                     const eofa_solve_params& P, int* updates);
+
 // Even-odd solve of D_T d = rhs (rhs = W.res), result added to W.x.
 CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
                    const eofa_solve_params& P, int* updates, int* fell_back) {
@@ -788,6 +800,8 @@ CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double 
         if (fb && fell_back) *fell_back = 1;
     } else if (P.prec == EOFA_FP64) {
         o = cg64(ctx, W, mp, mm, tol_n, maxit, check_every, P.use_graph != 0);
+    } else if (P.prec == EOFA_MIXED_FP16) {
+        o = cg_single_fp16(ctx, W, mp, mm, tol_n, maxit, check_every, P, updates);
     } else {
         o = cg_mixed(ctx, W, mp, mm, tol_n, maxit, check_every, P.reliable_delta, updates, P.use_graph != 0);
     }
@@ -865,11 +879,13 @@ struct Sys {
 void carve_batch(eofa_ctx* ctx, const eofa_solve_params& P, std::vector<Sys>& sys) {
     char* q = ctx->ws + base_bytes(ctx, &P);
     const size_t h64 = align_up(ctx->nh * sizeof(cd));
-    const size_t hk = align_up(ctx->nh * (P.prec != EOFA_FP64 ? sizeof(cpx<float>) : sizeof(cd)));
+    const size_t hxr = batch_vec_bytes(ctx, &P, true), hk = batch_vec_bytes(ctx, &P, false);
     for (Sys& y : sys) {
         y.xhi = (cd*)q; q += h64;
         y.bh = (cd*)q; q += h64;
-        void** v[7] = {&y.x, &y.r, &y.p, &y.u, &y.w, &y.wt, &y.at};
+        y.x = q; q += hxr;
+        y.r = q; q += hxr;
+        void** v[5] = {&y.p, &y.u, &y.w, &y.wt, &y.at};
         for (void** pp : v) { *pp = q; q += hk; }
     }
 }
@@ -893,15 +909,16 @@ template <typename R> HopArgsMR<R> mr_args(eofa_ctx* ctx, int par, int nr) {
     return a;
 }
 
-// One batched CG iteration over the systems (converged ones are skipped on the device).
-template <typename R> void cg_iteration_mr(eofa_ctx* ctx, std::vector<Sys>& sys) {
+// One batched CG iteration over the systems (converged ones are skipped on the device).  H: p, u, w,
+// wt, at in FP16 columns (R = float).
+template <typename R, bool H = false> void cg_iteration_mr(eofa_ctx* ctx, std::vector<Sys>& sys) {
     const int nr = (int)sys.size();
     auto V = [](void* p) { return (cpx<R>*)p; };
     {
         auto a = mr_args<R>(ctx, 0, nr);
         for (int r = 0; r < nr; r++) { a.in[r] = V(sys[r].p); a.out[r] = V(sys[r].u); a.opA[r] = sys[r].Ai; }
         a.cz = 1; a.caux = 0;
-        HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SITE, a, ctx->st));
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SITE, a, ctx->st, H));
     }
     {
         auto a = mr_args<R>(ctx, 1, nr);
@@ -910,13 +927,13 @@ template <typename R> void cg_iteration_mr(eofa_ctx* ctx, std::vector<Sys>& sys)
             a.opA[r] = sys[r].Ai; a.opB[r] = sys[r].Ad;
         }
         a.cz = (R)-0.25; a.caux = 1; a.epi = EPI_CG_W;
-        HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SCHUR_W, a, ctx->st));
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SCHUR_W, a, ctx->st, H));
     }
     {
         auto a = mr_args<R>(ctx, 0, nr);
         for (int r = 0; r < nr; r++) { a.in[r] = V(sys[r].wt); a.out[r] = V(sys[r].at); a.opA[r] = sys[r].Ad; }
         a.cz = 1; a.caux = 0;
-        HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SITE, a, ctx->st));
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SITE, a, ctx->st, H));
     }
     {
         auto a = mr_args<R>(ctx, 1, nr);
@@ -924,18 +941,25 @@ template <typename R> void cg_iteration_mr(eofa_ctx* ctx, std::vector<Sys>& sys)
             a.in[r] = V(sys[r].at); a.out[r] = V(sys[r].r); a.aux[r] = V(sys[r].w); a.aux2[r] = V(sys[r].r);
         }
         a.cz = (R)-0.25; a.caux = 1; a.epi = EPI_CG_R;
-        HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SCHUR_Q, a, ctx->st));
+        HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SCHUR_Q, a, ctx->st, H));
     }
     cpx<R>* xs[NRMAX];
     cpx<R>* ps[NRMAX];
     cpx<R>* rs[NRMAX];
     for (int r = 0; r < nr; r++) { xs[r] = V(sys[r].x); ps[r] = V(sys[r].p); rs[r] = V(sys[r].r); }
-    HIPCHK(launch_cg_xp_mr<R>(nr, xs, ps, rs, ctx->scal + BATCH_OFF, ctx->nh, ctx->st));
+    if constexpr (H) {
+        void* ph[NRMAX];
+        for (int r = 0; r < nr; r++) ph[r] = sys[r].p;
+        HIPCHK(launch_cg_xp_mr_h(ctx->Ns, nr, (cpx<float>* const*)xs, ph, (cpx<float>* const*)rs, ctx->scal + BATCH_OFF,
+                                 ctx->g.Vh, ctx->st));
+    } else {
+        HIPCHK(launch_cg_xp_mr<R>(nr, xs, ps, rs, ctx->scal + BATCH_OFF, ctx->nh, ctx->st));
+    }
 }
 
 // Batched CG on the systems' Schur normal equations to |r_normal| <= tol_n |r_normal,0| each.  With R = float
 // every system gets FP64 reliable updates (residual replacement) on its own schedule.
-template <typename R>
+template <typename R, bool H = false>
 void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_n, int maxit, int ce, double delta,
               bool graph = false) {
     const int nr = (int)sys.size();
@@ -962,7 +986,8 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
         }
         if (mixed) HIPCHK(launch_convert_d2f(W.r, (cpx<float>*)y.r, ctx->nh, ctx->st));
         else HIPCHK(hipMemcpyAsync(y.r, W.r, nb, hipMemcpyDeviceToDevice, ctx->st));
-        HIPCHK(hipMemcpyAsync(y.p, y.r, nb, hipMemcpyDeviceToDevice, ctx->st));
+        if constexpr (H) HIPCHK(launch_f2h(ctx->Ns, (const cpx<float>*)y.r, y.p, ctx->g.Vh, ctx->st));
+        else HIPCHK(hipMemcpyAsync(y.p, y.r, nb, hipMemcpyDeviceToDevice, ctx->st));
         arm(r, rr, rr);
     }
     int it = 0;
@@ -971,19 +996,19 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
         for (const Sys& y : sys) all &= y.conv;
         if (all) break;
         if (graph && it % ce == 0 && it + ce <= maxit) {
-            std::vector<uintptr_t> key = graph_key<R>(ctx, 3, ce, {});
+            std::vector<uintptr_t> key = graph_key<R>(ctx, H ? 4 : 3, ce, {});
             for (const Sys& y : sys)
                 for (const void* q : {(const void*)y.Ai, (const void*)y.Ad, (const void*)y.x, (const void*)y.r,
                                       (const void*)y.p, (const void*)y.u, (const void*)y.w, (const void*)y.wt,
                                       (const void*)y.at})
                     key.push_back((uintptr_t)q);
             graph_run(ctx, std::move(key), [&] {
-                for (int k = 0; k < ce; k++) cg_iteration_mr<R>(ctx, sys);
+                for (int k = 0; k < ce; k++) cg_iteration_mr<R, H>(ctx, sys);
             });
             it += ce;
             for (Sys& y : sys) if (!y.conv) y.iters += ce;
         } else {
-            cg_iteration_mr<R>(ctx, sys);
+            cg_iteration_mr<R, H>(ctx, sys);
             it++;
             for (Sys& y : sys) if (!y.conv) y.iters++;
         }
@@ -1017,6 +1042,28 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
             if (!y.conv) HIPCHK(launch_accum_f(y.xhi, (const cpx<float>*)y.x, ctx->nh, ctx->st));
 }
 
+// Dhat W.xcg = W.bh with FP16-column Krylov vectors: a one-system batch (FP64 reliable updates)
+CgOut cg_single_fp16(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int ce,
+                     const eofa_solve_params& P, int* updates) {
+    std::vector<Sys> sys(1);
+    carve_batch(ctx, P, sys);
+    ensure_partials_mr(ctx);
+    Sys& y = sys[0];
+    y.mp = mp;
+    y.mm = mm;
+    y.Ai = site_tab(ctx, SK_AINV, mp, mm);
+    y.Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+    y.bh = W.bh;
+    cg_batch<float, true>(ctx, W, sys, tol_n, maxit, ce, P.reliable_delta, P.use_graph != 0);
+    HIPCHK(hipMemcpyAsync(W.xcg, y.xhi, ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+    CgOut o;
+    o.iters = y.iters;
+    o.applies = 2 * y.iters + 2 * y.updates + 2;
+    o.converged = y.conv;
+    if (updates) *updates += y.updates;
+    return o;
+}
+
 void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
     REQUIRE(P != nullptr, EOFA_EINVAL, "params is NULL");
     REQUIRE(P->tol > 0 && P->tol < 1, EOFA_EINVAL, "tol must be in (0, 1)");
@@ -1028,7 +1075,8 @@ void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
 }
 
 SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
-    REQUIRE(P.prec == EOFA_FP64 || P.prec == EOFA_MIXED_FP32, EOFA_ENOTIMPL, "EOFA_MIXED_FP16 is not available in this build");
+    if (P.prec == EOFA_MIXED_FP16)
+        REQUIRE(ctx->Ns >= 8 && ctx->Ns % 8 == 0, EOFA_EINVAL, "EOFA_MIXED_FP16 needs Ns in {8, 16, 32}");
     if (P.pc == EOFA_PC_LEARNED) {
         REQUIRE(ctx->cnn.ready, EOFA_ESTATE, "learned preconditioner: no weights (eofa_cnn_init or eofa_set_precond)");
         REQUIRE(ctx->Ns % 8 == 0, EOFA_EINVAL, "learned preconditioner needs Ns % 8 == 0");
@@ -1131,7 +1179,7 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
                               double* S, const eofa_solve_params* P, eofa_solve_info* info) {
     check_params(ctx, P);
     for (int j = 0; j < n; j++) check_action(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j]);
-    if (n <= 1 || ctx->Ns < 8 || P->pc != EOFA_PC_NONE) {
+    if ((n <= 1 && P->prec != EOFA_MIXED_FP16) || ctx->Ns < 8 || P->pc != EOFA_PC_NONE) {
         eofa_status worst = EOFA_OK;
         for (int j = 0; j < n; j++) {
             double sj = 0;
@@ -1165,6 +1213,8 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
         const double tol_n = 0.25 * P->tol;
         const int ce = auto_check_every(ctx, *P);
         if (P->prec == EOFA_FP64) cg_batch<double>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
+        else if (P->prec == EOFA_MIXED_FP16)
+            cg_batch<float, true>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
         else cg_batch<float>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
         HIPCHK(hipStreamSynchronize(ctx->st));
         const double tb = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() / nr;

@@ -61,7 +61,16 @@ template <typename R> struct HopArgsMR {
     int pstride;
     int epi;            // reduction epilogue (EPI_CG_W / EPI_CG_R) for the reducing modes
 };
-template <typename R> hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipStream_t st);
+// half: FP16-column Krylov fields (R = float; see load_h / store_h in kernels.hip)
+template <typename R> hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipStream_t st,
+                                               bool half = false);
+// FP16 bytes of one half field: 12 Vh Ns (re, im) binary16 pairs + Vh Ns FP32 column norms
+inline size_t half_field_bytes_h(const Geom& g, int Ns) { return (size_t)g.Vh * Ns * (12 * 4 + 4); }
+// x_r (FP32) += alpha_r p_r ; p_r (FP16 columns) = r_r (FP32) + beta_r p_r, then SC_DONEX = SC_DONE
+hipError_t launch_cg_xp_mr_h(int Ns, int nr, cpx<float>* const* x, void* const* p, cpx<float>* const* r, double* scal,
+                             int Vh, hipStream_t st);
+hipError_t launch_f2h(int Ns, const cpx<float>* in, void* out, int Vh, hipStream_t st);
+hipError_t launch_h2d(int Ns, const void* in, cd* out, int Vh, hipStream_t st);
 // x_r += alpha_r p_r ; p_r = r_r + beta_r p_r for the systems whose SC_DONEX is clear, then SC_DONEX = SC_DONE
 template <typename R> hipError_t launch_cg_xp_mr(int nr, cpx<R>* const* x, cpx<R>* const* p, cpx<R>* const* r,
                                                  double* scal, size_t n, hipStream_t st);

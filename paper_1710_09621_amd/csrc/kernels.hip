@@ -22,18 +22,76 @@ namespace eofa {
 #define HOP_LDS_LINKS 1
 #endif
 
+// ---- FP16 storage of a Krylov half field (EOFA_MIXED_FP16): F[cb][12][Ns] as (re, im) pairs of
+// binary16, each (cb, s) column scaled by its own FP32 norm = the largest |real component| of its 24
+// reals, stored after the 12 Vh Ns pairs.  value = norm * half, |half| <= 1.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+template <int NS> __device__ __forceinline__ const float* h_norms(const void* f, int Vh) {
+    return (const float*)((const h2_t*)f + (size_t)12 * Vh * NS);
+}
+
+template <int NS>
+__device__ __forceinline__ void load_h(cpx<float> p[12], const void* __restrict__ f, size_t cb, int s, int Vh) {
+    const h2_t* d = (const h2_t*)f + cb * 12 * NS + s;
+    const float n = h_norms<NS>(f, Vh)[cb * NS + s];
+#pragma unroll
+    for (int j = 0; j < 12; j++) {
+        const h2_t v = d[j * NS];
+        p[j] = {n * (float)v.x, n * (float)v.y};
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ void store_h(void* __restrict__ f, size_t cb, int s, int Vh, const cpx<float> v[12]) {
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 12; j++) m = fmaxf(m, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
+    const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+    h2_t* d = (h2_t*)f + cb * 12 * NS + s;
+#pragma unroll
+    for (int j = 0; j < 12; j++) {
+        h2_t h;
+        h.x = (_Float16)(v[j].x * inv);
+        h.y = (_Float16)(v[j].y * inv);
+        d[j * NS] = h;
+    }
+    ((float*)h_norms<NS>(f, Vh))[cb * NS + s] = m;
+}
+
+// 12 components of (cb, s) from a field in storage H (FP16 columns) or plain cpx<R>
+template <int NS, bool H, typename R>
+__device__ __forceinline__ void load_col(cpx<R> p[12], const void* __restrict__ f, size_t cb, int s, int Vh) {
+    if constexpr (H) {
+        load_h<NS>(p, f, cb, s, Vh);
+    } else {
+        const cpx<R>* src = (const cpx<R>*)f + cb * 12 * NS + s;
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+    }
+}
+
+template <int NS, bool H, typename R>
+__device__ __forceinline__ void store_col(void* __restrict__ f, size_t cb, int s, int Vh, const cpx<R> v[12]) {
+    if constexpr (H) {
+        store_h<NS>(f, cb, s, Vh, v);
+    } else {
+        cpx<R>* dst = (cpx<R>*)f + cb * 12 * NS + s;
+#pragma unroll
+        for (int j = 0; j < 12; j++) dst[j * NS] = v[j];
+    }
+}
+
 // One direction mu of the hop: forward (1 - S gamma) U in(x+mu) and backward (1 + S gamma) U^dag in(x-mu).
 // Uf / Ub point at the 9 complex entries of U_mu(x) and U_mu(x-mu) (global memory or LDS).
-template <int NS, bool DAG, int MU, typename R>
+template <int NS, bool DAG, int MU, typename R, bool H = false>
 __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict__ in, const cpx<R>* Uf,
-                                       const cpx<R>* Ub, const int nb[8], int s) {
+                                       const cpx<R>* Ub, const int nb[8], int s, int Vh = 0) {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     {
-        const cpx<R>* src = in + (size_t)nb[2 * MU] * 12 * NS + s;
         cpx<R> p[12];
-#pragma unroll
-        for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+        load_col<NS, H>(p, in, (size_t)nb[2 * MU], s, Vh);
         cpx<R> h[6], w[6], U[9];
         project<MU, SF>(p, h);
 #pragma unroll
@@ -42,10 +100,8 @@ __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict_
         reconstruct<MU, SF>(acc, w);
     }
     {
-        const cpx<R>* src = in + (size_t)nb[2 * MU + 1] * 12 * NS + s;
         cpx<R> p[12];
-#pragma unroll
-        for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+        load_col<NS, H>(p, in, (size_t)nb[2 * MU + 1], s, Vh);
         cpx<R> h[6], w[6], U[9];
         project<MU, SB>(p, h);
 #pragma unroll
@@ -110,12 +166,20 @@ __device__ __forceinline__ void stage_links(cpx<R> (*sU)[8][9], const cpx<R>* __
 }
 
 // z = hop(in) at (cb, s) with the links of this lane's site in sUl[8][9].
-template <int NS, bool DAG, typename R>
+template <int NS, bool DAG, typename R, bool H = false>
 __device__ __forceinline__ void hop_lds(cpx<R> z[12], const cpx<R>* __restrict__ in, const cpx<R> (*sUl)[9],
-                                        const int nb[8], int s) {
+                                        const int nb[8], int s, int Vh = 0) {
 #pragma unroll
     for (int j = 0; j < 12; j++) z[j] = {0, 0};
-    if constexpr (HOP_PIPE) {
+    if constexpr (H) {
+        hop_mu<NS, DAG, 0, R, H>(z, in, sUl[0], sUl[4], nb, s, Vh);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 1, R, H>(z, in, sUl[1], sUl[5], nb, s, Vh);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 2, R, H>(z, in, sUl[2], sUl[6], nb, s, Vh);
+        HOP_FENCE();
+        hop_mu<NS, DAG, 3, R, H>(z, in, sUl[3], sUl[7], nb, s, Vh);
+    } else if constexpr (HOP_PIPE) {
         cpx<R> cur[12];
         load_spinor<NS>(cur, in, nb[0], s);
         hop_pipe<NS, DAG, 0>(z, cur, in, sUl, nb, s);
@@ -267,7 +331,9 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
 }
 
 // ===================================================================== multi-RHS hop
-template <int NS, bool DAG, int MODE, typename R>
+// With H (R = float only) the Krylov fields in, out (not HM_SCHUR_Q), out2 and aux are FP16 columns;
+// the residual (aux2 and the output of HM_SCHUR_Q) stays FP32.
+template <int NS, bool DAG, int MODE, typename R, bool H>
 __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a) {
     const int tid = tile_of(blockIdx.x, gridDim.x, a.sc, a.g) * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -285,7 +351,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
         const double* S = a.scal + r * SC_N;
         if (S[SC_DONE] != 0.0) continue;  // uniform over the grid
         cpx<R> z[12], v[12];
-        hop_lds<NS, DAG>(z, a.in[r], sU[threadIdx.x / NS], nb, s);
+        hop_lds<NS, DAG, R, H>(z, a.in[r], sU[threadIdx.x / NS], nb, s, a.g.Vh);
         double nrm = 0.0;
         if constexpr (MODE == HM_SITE) {
 #pragma unroll
@@ -293,41 +359,34 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
             site_op<NS, DAG>(v, *a.opA[r], s, lane);
         } else if constexpr (MODE == HM_SCHUR_W) {
             site_op<NS, false>(z, *a.opA[r], s, lane);
-            const cpx<R>* aux = a.aux[r] + base;
+            cpx<R> t[12];
+            load_col<NS, H>(t, a.aux[r], (size_t)cb, s, a.g.Vh);
 #pragma unroll
             for (int j = 0; j < 12; j++) {
-                cpx<R> t = aux[j * NS];
-                v[j].x = fma(a.cz, z[j].x, a.caux * t.x);
-                v[j].y = fma(a.cz, z[j].y, a.caux * t.y);
+                v[j].x = fma(a.cz, z[j].x, a.caux * t[j].x);
+                v[j].y = fma(a.cz, z[j].y, a.caux * t[j].y);
             }
         } else {  // HM_SCHUR_Q
             const R alpha = (R)S[SC_ALPHA];
-            const cpx<R>* aux = a.aux[r] + base;
+            cpx<R> w[12];
+            load_col<NS, H>(w, a.aux[r], (size_t)cb, s, a.g.Vh);
             const cpx<R>* aux2 = a.aux2[r] + base;
 #pragma unroll
             for (int j = 0; j < 12; j++) {
-                cpx<R> w = aux[j * NS], rr = aux2[j * NS];
-                R qx = fma(a.cz, z[j].x, a.caux * w.x), qy = fma(a.cz, z[j].y, a.caux * w.y);
+                cpx<R> rr = aux2[j * NS];
+                R qx = fma(a.cz, z[j].x, a.caux * w[j].x), qy = fma(a.cz, z[j].y, a.caux * w[j].y);
                 v[j].x = fma(-alpha, qx, rr.x);
                 v[j].y = fma(-alpha, qy, rr.y);
             }
         }
-        if (valid) {
-            cpx<R>* out = a.out[r] + base;
-#pragma unroll
-            for (int j = 0; j < 12; j++) out[j * NS] = v[j];
-        }
+        if (valid) store_col<NS, H && MODE != HM_SCHUR_Q>(a.out[r], (size_t)cb, s, a.g.Vh, v);
         if constexpr (MODE != HM_SITE) {
 #pragma unroll
             for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
             if (!valid) nrm = 0.0;
             if constexpr (MODE == HM_SCHUR_W) {
                 site_op<NS, true>(v, *a.opB[r], s, lane);
-                if (valid) {
-                    cpx<R>* o2 = a.out2[r] + base;
-#pragma unroll
-                    for (int j = 0; j < 12; j++) o2[j * NS] = v[j];
-                }
+                if (valid) store_col<NS, H>(a.out2[r], (size_t)cb, s, a.g.Vh, v);
             }
             const double bs = block_sum256(nrm, lds);
             if (threadIdx.x == 0) a.partials[(size_t)r * a.pstride + blockIdx.x] = bs;
@@ -363,6 +422,56 @@ __global__ __launch_bounds__(256) void k_cg_xp_mr(const XpArgs<R> a, double* sca
         xx.x = fma(alpha, pp.x, xx.x); xx.y = fma(alpha, pp.y, xx.y);
         pp.x = fma(beta, pp.x, q.x);   pp.y = fma(beta, pp.y, q.y);
         x[i] = xx; p[i] = pp;
+    }
+}
+
+// FP16 form: x (FP32) += alpha p ; p (FP16 columns) = r (FP32) + beta p; one thread per (cb, s)
+template <int NS>
+__global__ __launch_bounds__(256) void k_cg_xp_mr_h(const XpArgs<float> a, double* scal, int Vh) {
+    const int r = blockIdx.y;
+    const double* S = scal + r * SC_N;
+    if (S[SC_DONEX] != 0.0) return;
+    const float alpha = (float)S[SC_ALPHA], beta = (float)S[SC_BETA];
+    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < (size_t)Vh * NS; t += (size_t)gridDim.x * 256) {
+        const size_t cb = t / NS;
+        const int s = (int)(t % NS);
+        cpx<float> p[12], x[12], q[12];
+        load_h<NS>(p, a.p[r], cb, s, Vh);
+        load_col<NS, false>(x, a.x[r], cb, s, Vh);
+        load_col<NS, false>(q, a.r[r], cb, s, Vh);
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            x[j].x = fmaf(alpha, p[j].x, x[j].x); x[j].y = fmaf(alpha, p[j].y, x[j].y);
+            p[j].x = fmaf(beta, p[j].x, q[j].x);  p[j].y = fmaf(beta, p[j].y, q[j].y);
+        }
+        store_col<NS, false>(a.x[r], cb, s, Vh, x);
+        store_h<NS>(a.p[r], cb, s, Vh, p);
+    }
+}
+
+// FP32 half field -> FP16 columns
+template <int NS>
+__global__ __launch_bounds__(256) void k_f2h(const cpx<float>* __restrict__ in, void* __restrict__ out, int Vh) {
+    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < (size_t)Vh * NS; t += (size_t)gridDim.x * 256) {
+        const size_t cb = t / NS;
+        const int s = (int)(t % NS);
+        cpx<float> v[12];
+        load_col<NS, false>(v, in, cb, s, Vh);
+        store_h<NS>(out, cb, s, Vh, v);
+    }
+}
+
+// FP16 columns -> FP64 half field (diagnostics and tests)
+template <int NS>
+__global__ __launch_bounds__(256) void k_h2d(const void* __restrict__ in, cd* __restrict__ out, int Vh) {
+    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < (size_t)Vh * NS; t += (size_t)gridDim.x * 256) {
+        const size_t cb = t / NS;
+        const int s = (int)(t % NS);
+        cpx<float> v[12];
+        load_h<NS>(v, in, cb, s, Vh);
+        cd* dst = out + cb * 12 * NS + s;
+#pragma unroll
+        for (int j = 0; j < 12; j++) dst[j * NS] = {(double)v[j].x, (double)v[j].y};
     }
 }
 
@@ -721,11 +830,18 @@ template hipError_t launch_hop<double>(int, bool, int, bool, const HopArgs<doubl
 template hipError_t launch_hop<float>(int, bool, int, bool, const HopArgs<float>&, hipStream_t);
 
 template <typename R>
-hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipStream_t st) {
+hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipStream_t st, bool half) {
     if (a.nr < 1 || a.nr > NRMAX) return hipErrorInvalidValue;
+    if (half && sizeof(R) != 4) return hipErrorInvalidValue;
     const int grid = (int)(((size_t)a.g.Vh * Ns + 255) / 256);
     if (grid > a.pstride) return hipErrorInvalidValue;
-#define MR_L(D, M) hipLaunchKernelGGL((k_hop_mr<NS, D, M, R>), dim3(grid), dim3(256), 0, st, a)
+#define MR_L(D, M)                                                                                       \
+    do {                                                                                                 \
+        if constexpr (sizeof(R) == 4) {                                                                  \
+            if (half) { hipLaunchKernelGGL((k_hop_mr<NS, D, M, R, true>), dim3(grid), dim3(256), 0, st, a); break; } \
+        }                                                                                                \
+        hipLaunchKernelGGL((k_hop_mr<NS, D, M, R, false>), dim3(grid), dim3(256), 0, st, a);            \
+    } while (0)
 #define MR_MODES(D)                                            \
     switch (mode) {                                            \
     case HM_SITE: MR_L(D, HM_SITE); break;                     \
@@ -746,8 +862,36 @@ hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipS
                            a.epi);
     return hipGetLastError();
 }
-template hipError_t launch_hop_mr<double>(int, bool, int, const HopArgsMR<double>&, hipStream_t);
-template hipError_t launch_hop_mr<float>(int, bool, int, const HopArgsMR<float>&, hipStream_t);
+template hipError_t launch_hop_mr<double>(int, bool, int, const HopArgsMR<double>&, hipStream_t, bool);
+template hipError_t launch_hop_mr<float>(int, bool, int, const HopArgsMR<float>&, hipStream_t, bool);
+
+hipError_t launch_cg_xp_mr_h(int Ns, int nr, cpx<float>* const* x, void* const* p, cpx<float>* const* r, double* scal,
+                             int Vh, hipStream_t st) {
+    if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
+    XpArgs<float> a{};
+    for (int i = 0; i < nr; i++) { a.x[i] = x[i]; a.p[i] = (cpx<float>*)p[i]; a.r[i] = r[i]; }
+    const int gx = nblk((size_t)Vh * Ns) > 1024 ? 1024 : nblk((size_t)Vh * Ns);
+    switch (Ns) {
+    case 8: hipLaunchKernelGGL((k_cg_xp_mr_h<8>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
+    case 16: hipLaunchKernelGGL((k_cg_xp_mr_h<16>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
+    case 32: hipLaunchKernelGGL((k_cg_xp_mr_h<32>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_sync_done, dim3(1), dim3(64), 0, st, scal, nr);
+    return hipGetLastError();
+}
+
+hipError_t launch_f2h(int Ns, const cpx<float>* in, void* out, int Vh, hipStream_t st) {
+    const int g = nblk((size_t)Vh * Ns);
+    NS_SWITCH(Ns, hipLaunchKernelGGL((k_f2h<NS>), dim3(g), dim3(256), 0, st, in, out, Vh));
+    return hipGetLastError();
+}
+
+hipError_t launch_h2d(int Ns, const void* in, cd* out, int Vh, hipStream_t st) {
+    const int g = nblk((size_t)Vh * Ns);
+    NS_SWITCH(Ns, hipLaunchKernelGGL((k_h2d<NS>), dim3(g), dim3(256), 0, st, in, out, Vh));
+    return hipGetLastError();
+}
 
 template <typename R>
 hipError_t launch_cg_xp_mr(int nr, cpx<R>* const* x, cpx<R>* const* p, cpx<R>* const* r, double* scal, size_t n,
