@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=50000)
     ap.add_argument("--tune-cache", type=str, default=None)
+    ap.add_argument("--tuned-prec", choices=("fp16", "fp32"), default="fp16",
+                    help="Krylov storage of the tuned solver (FP32 arithmetic and FP64 reliable updates either way)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "hop_traffic.json"),
                     help="JSON with measured HBM bytes per hop launch (from rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -119,11 +121,12 @@ def main():
         actions = [(-1, m, m, M), (+1, m, M, M)]
         wl = f"EOFA (m, m)/(M, M) = ({m}, {M}) without MP, 2 chiral actions"
     P64 = E.params(tol=1e-10, max_iter=args.max_iter)
-    PT = E.params(tol=1e-10, max_iter=args.max_iter, prec=E.MIXED_FP32)
+    tuned_prec = {"fp16": E.MIXED_FP16, "fp32": E.MIXED_FP32}[args.tuned_prec]
+    PT = E.params(tol=1e-10, max_iter=args.max_iter, prec=tuned_prec)
 
     # hop-kernel schedules for this lattice (in-house autotuner), outside the timed region
     tune = {}
-    for prec, nm in ((E.FP64, "fp64"), (E.MIXED_FP32, "fp32")):
+    for prec, nm in ((E.FP64, "fp64"), (tuned_prec, args.tuned_prec)):
         tune[nm] = ctx.autotune(prec=prec, cache=args.tune_cache)
         log(f"autotune {nm}: {tune[nm]}")
 
@@ -219,7 +222,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(per_launch_ms, 5)},
         "tts": {"plain_fp64_s_per_step": round(tp / args.steps, 3), "plain_iters": iters,
                 "tuned_s_per_step": round(tt / args.steps, 3), "tuned_iters": iters_t,
-                "tuned": "multi-RHS batch (all systems of the step in one launch sequence), FP32-storage "
+                "tuned": f"multi-RHS batch (all systems of the step in one launch sequence), {args.tuned_prec.upper()}-storage "
                          "reliable-update CG, autotuned hop schedule",
                 "speedup": round(tp / tt, 3), "max_true_rel_resid": max(resid), "max_rel_dS": dS,
                 "schedules": {k: v["sched"] for k, v in tune.items()}},

@@ -165,14 +165,16 @@ eofa_status eofa_hop_timing_reset(eofa_ctx *ctx);
 eofa_status eofa_graph_stats(eofa_ctx *ctx, long *replays, int *cached);
 
 /* Diagnostic: nrep back-to-back launches of the fused even-odd hop with its A_T^{-1} epilogue
- * (u = A_T^{-1} H_eo p, alternating parities, masses 0.01) on workspace buffers, in EOFA_FP64 or
- * EOFA_MIXED_FP32 storage.  *ms = average device time per launch (HIP events), *alg_bytes =
- * algorithmic HBM bytes of one launch (input and output half fields + 8 links per 4D site). */
+ * (u = A_T^{-1} H_eo p, alternating parities, masses 0.01) on workspace buffers, in EOFA_FP64,
+ * EOFA_MIXED_FP32 or EOFA_MIXED_FP16 storage (FP16: the batch kernel with one system, FP32 links).
+ * *ms = average device time per launch (HIP events), *alg_bytes = algorithmic HBM bytes of one
+ * launch (input and output half fields + 8 links per 4D site). */
 eofa_status eofa_dslash_bench(eofa_ctx *ctx, int prec, int nrep, double *ms, double *alg_bytes);
 
 /*
  * Autotuner of the hop kernels' workgroup schedule (XCD-contiguous ranges, 3D tiling of the
- * workgroup grid) for this lattice and storage precision: times every candidate with
+ * workgroup grid) for this lattice and storage precision (FP64, FP32 or FP16; each has its own
+ * schedule, FP16 for the batch kernels): times every candidate with
  * nrep launches of the fused hop (0: 4) and keeps the fastest for all later solves.
  * sched_out[7] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb, ord} for a persistent cache;
  * *best_ms / *base_ms (may be NULL) the chosen and the linear-order launch times.

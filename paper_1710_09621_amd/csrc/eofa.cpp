@@ -73,9 +73,9 @@ struct eofa_ctx {
     hipStream_t cap_st = nullptr;
     std::map<std::vector<uintptr_t>, hipGraphExec_t> graphs;
     long graph_replays = 0;
-    // workgroup schedules of the hop kernels, per storage precision (0: FP64, 1: FP32); set by the autotuner
-    Sched sched[2] = {{0, 0, 1, 1, 1, 1, 0}, {0, 0, 1, 1, 1, 1, 0}};
-    double tuned_ms[2] = {0, 0};
+    // workgroup schedules of the hop kernels per storage (0: FP64, 1: FP32, 2: FP16 columns), set by the autotuner
+    Sched sched[3] = {{0, 0, 1, 1, 1, 1, 0}, {0, 0, 1, 1, 1, 1, 0}, {0, 0, 1, 1, 1, 1, 0}};
+    double tuned_ms[3] = {0, 0, 0};
 };
 
 namespace {
@@ -330,10 +330,10 @@ template <typename F> void graph_run(eofa_ctx* ctx, std::vector<uintptr_t> key, 
 }
 
 template <typename R> std::vector<uintptr_t> graph_key(const eofa_ctx* ctx, int kind, int n,
-                                                       std::initializer_list<const void*> ptrs) {
+                                                       std::initializer_list<const void*> ptrs, bool half = false) {
     std::vector<uintptr_t> k{(uintptr_t)kind, (uintptr_t)n, sizeof(R), (uintptr_t)ctx->scal,
                              (uintptr_t)ctx->partials, (uintptr_t)ctx->partials_mr, (uintptr_t)ctx->pstride};
-    const Sched& sc = ctx->sched[sizeof(R) == 8 ? 0 : 1];
+    const Sched& sc = ctx->sched[half ? 2 : (sizeof(R) == 8 ? 0 : 1)];
     for (int v : {sc.mode, sc.xcd, sc.ty, sc.tz, sc.tt, sc.nyb, sc.ord}) k.push_back((uintptr_t)v);
     for (const void* p : ptrs) k.push_back((uintptr_t)p);
     return k;
@@ -899,10 +899,10 @@ void sync_scal_batch(eofa_ctx* ctx, int nr) {
     HIPCHK(hipStreamSynchronize(ctx->st));
 }
 
-template <typename R> HopArgsMR<R> mr_args(eofa_ctx* ctx, int par, int nr) {
+template <typename R> HopArgsMR<R> mr_args(eofa_ctx* ctx, int par, int nr, bool half = false) {
     HopArgsMR<R> a{};
     HopArgs<R> b = hop_args<R>(ctx, par);
-    a.g = b.g; a.sc = b.sc; a.par = par; a.nr = nr; a.Uown = b.Uown; a.Uoth = b.Uoth;
+    a.g = b.g; a.sc = half ? ctx->sched[2] : b.sc; a.par = par; a.nr = nr; a.Uown = b.Uown; a.Uoth = b.Uoth;
     a.scal = ctx->scal + BATCH_OFF;
     a.partials = ctx->partials_mr;
     a.pstride = ctx->pstride;
@@ -915,13 +915,13 @@ template <typename R, bool H = false> void cg_iteration_mr(eofa_ctx* ctx, std::v
     const int nr = (int)sys.size();
     auto V = [](void* p) { return (cpx<R>*)p; };
     {
-        auto a = mr_args<R>(ctx, 0, nr);
+        auto a = mr_args<R>(ctx, 0, nr, H);
         for (int r = 0; r < nr; r++) { a.in[r] = V(sys[r].p); a.out[r] = V(sys[r].u); a.opA[r] = sys[r].Ai; }
         a.cz = 1; a.caux = 0;
         HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SITE, a, ctx->st, H));
     }
     {
-        auto a = mr_args<R>(ctx, 1, nr);
+        auto a = mr_args<R>(ctx, 1, nr, H);
         for (int r = 0; r < nr; r++) {
             a.in[r] = V(sys[r].u); a.out[r] = V(sys[r].w); a.out2[r] = V(sys[r].wt); a.aux[r] = V(sys[r].p);
             a.opA[r] = sys[r].Ai; a.opB[r] = sys[r].Ad;
@@ -930,13 +930,13 @@ template <typename R, bool H = false> void cg_iteration_mr(eofa_ctx* ctx, std::v
         HIPCHK(launch_hop_mr<R>(ctx->Ns, false, HM_SCHUR_W, a, ctx->st, H));
     }
     {
-        auto a = mr_args<R>(ctx, 0, nr);
+        auto a = mr_args<R>(ctx, 0, nr, H);
         for (int r = 0; r < nr; r++) { a.in[r] = V(sys[r].wt); a.out[r] = V(sys[r].at); a.opA[r] = sys[r].Ad; }
         a.cz = 1; a.caux = 0;
         HIPCHK(launch_hop_mr<R>(ctx->Ns, true, HM_SITE, a, ctx->st, H));
     }
     {
-        auto a = mr_args<R>(ctx, 1, nr);
+        auto a = mr_args<R>(ctx, 1, nr, H);
         for (int r = 0; r < nr; r++) {
             a.in[r] = V(sys[r].at); a.out[r] = V(sys[r].r); a.aux[r] = V(sys[r].w); a.aux2[r] = V(sys[r].r);
         }
@@ -996,7 +996,7 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
         for (const Sys& y : sys) all &= y.conv;
         if (all) break;
         if (graph && it % ce == 0 && it + ce <= maxit) {
-            std::vector<uintptr_t> key = graph_key<R>(ctx, H ? 4 : 3, ce, {});
+            std::vector<uintptr_t> key = graph_key<R>(ctx, H ? 4 : 3, ce, {}, H);
             for (const Sys& y : sys)
                 for (const void* q : {(const void*)y.Ai, (const void*)y.Ad, (const void*)y.x, (const void*)y.r,
                                       (const void*)y.p, (const void*)y.u, (const void*)y.w, (const void*)y.wt,
@@ -1260,13 +1260,20 @@ double time_hop(eofa_ctx* ctx, int prec, int nrep, const Sched& sc) {
                 a.sc = sc;
                 a.in = par ? W.u : W.p; a.out = par ? W.p : W.u; a.opA = Ai; a.cz = 1.0; a.caux = 0.0;
                 HIPCHK(launch_hop<double>(ctx->Ns, false, HM_SITE, false, a, ctx->st));
-            } else {
+            } else if (prec == EOFA_MIXED_FP32) {
                 auto a = hop_args<float>(ctx, par);
                 a.sc = sc;
                 cpx<float>* pf = (cpx<float>*)W.p;
                 cpx<float>* uf = (cpx<float>*)W.u;
                 a.in = par ? uf : pf; a.out = par ? pf : uf; a.opA = Ai; a.cz = 1.0f; a.caux = 0.0f;
                 HIPCHK(launch_hop<float>(ctx->Ns, false, HM_SITE, false, a, ctx->st));
+            } else {  // FP16 columns through the batch kernel, one system
+                auto a = mr_args<float>(ctx, par, 1, true);
+                a.sc = sc;
+                cpx<float>* pf = (cpx<float>*)W.p;
+                cpx<float>* uf = (cpx<float>*)W.u;
+                a.in[0] = par ? uf : pf; a.out[0] = par ? pf : uf; a.opA[0] = Ai; a.cz = 1.0f; a.caux = 0.0f;
+                HIPCHK(launch_hop_mr<float>(ctx->Ns, false, HM_SITE, a, ctx->st, true));
             }
         }
     };
@@ -1608,13 +1615,17 @@ eofa_status eofa_dslash_bench(eofa_ctx* ctx, int prec, int nrep, double* ms, dou
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
         REQUIRE(nrep > 0 && ms, EOFA_EINVAL, "bad arguments");
-        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32 || (prec == EOFA_MIXED_FP16 && ctx->Ns >= 8),
+                EOFA_EINVAL, "prec must be FP64, MIXED_FP32 or MIXED_FP16 (Ns >= 8)");
         eofa_solve_params P{1e-10, 1, (eofa_precision)prec, EOFA_PC_NONE, 0, 0, 0};
         ensure_ws(ctx, needed_bytes(ctx, &P));
+        if (prec == EOFA_MIXED_FP16) ensure_partials_mr(ctx);
         fill_bench_buffers(ctx);
-        *ms = time_hop(ctx, prec, nrep, ctx->sched[prec == EOFA_FP64 ? 0 : 1]);
-        const double rs = (prec == EOFA_FP64) ? 16.0 : 8.0;
-        if (alg_bytes) *alg_bytes = (double)ctx->g.Vh * (2.0 * 12 * ctx->Ns * rs + 8 * 9 * rs);
+        *ms = time_hop(ctx, prec, nrep, ctx->sched[prec]);
+        // in + out spinor columns and 8 links per 4D site (FP16 columns: 48 B + a 4-byte norm; FP32 links)
+        const double col = (prec == EOFA_FP64) ? 12 * 16.0 : (prec == EOFA_MIXED_FP32 ? 12 * 8.0 : 12 * 4.0 + 4.0);
+        const double lk = (prec == EOFA_FP64) ? 16.0 : 8.0;
+        if (alg_bytes) *alg_bytes = (double)ctx->g.Vh * (2.0 * ctx->Ns * col + 8 * 9 * lk);
         return EOFA_OK;
     });
 }
@@ -1622,12 +1633,14 @@ eofa_status eofa_dslash_bench(eofa_ctx* ctx, int prec, int nrep, double* ms, dou
 eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[7], double* best_ms, double* base_ms) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
-        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32 || (prec == EOFA_MIXED_FP16 && ctx->Ns >= 8),
+                EOFA_EINVAL, "prec must be FP64, MIXED_FP32 or MIXED_FP16 (Ns >= 8)");
         if (nrep <= 0) nrep = 4;
         eofa_solve_params P{1e-10, 1, (eofa_precision)prec, EOFA_PC_NONE, 0, 0, 0};
         ensure_ws(ctx, needed_bytes(ctx, &P));
+        if (prec == EOFA_MIXED_FP16) ensure_partials_mr(ctx);
         fill_bench_buffers(ctx);
-        const int k = prec == EOFA_FP64 ? 0 : 1;
+        const int k = prec;
         std::vector<Sched> cand = sched_candidates(ctx);
         double best = 1e30, base = 0;
         Sched bs = cand[0];
@@ -1651,14 +1664,15 @@ eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[7], d
 eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[7]) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(sched_in, EOFA_EINVAL, "null schedule");
-        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be FP64 or MIXED_FP32");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32 || prec == EOFA_MIXED_FP16, EOFA_EINVAL,
+                "prec must be FP64, MIXED_FP32 or MIXED_FP16");
         Sched s{sched_in[0], sched_in[1], sched_in[2], sched_in[3], sched_in[4], sched_in[5], sched_in[6]};
         bool ok = false;
         for (const Sched& c : sched_candidates(ctx))
             ok |= (c.mode == s.mode && c.xcd == s.xcd && c.ty == s.ty && c.tz == s.tz && c.tt == s.tt &&
                    c.nyb == s.nyb && c.ord == s.ord);
         REQUIRE(ok, EOFA_EINVAL, "schedule not valid for this lattice");
-        ctx->sched[prec == EOFA_FP64 ? 0 : 1] = s;
+        ctx->sched[prec] = s;
         return EOFA_OK;
     });
 }
