@@ -22,23 +22,50 @@ namespace eofa {
 #define HOP_LDS_LINKS 1
 #endif
 
-// ---- FP16 storage of a Krylov half field (EOFA_MIXED_FP16): F[cb][12][Ns] as (re, im) pairs of
-// binary16, each (cb, s) column scaled by its own FP32 norm = the largest |real component| of its 24
-// reals, stored after the 12 Vh Ns pairs.  value = norm * half, |half| <= 1.
-typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+// Cache policy of the hop's streams: the outputs are not read again by the same launch and the links
+// are read once per workgroup, so both may bypass the caches that hold the re-read neighbour spinors.
+#ifndef HOP_NT_STORE
+#define HOP_NT_STORE 1
+#endif
+#ifndef HOP_NT_LINKS
+#define HOP_NT_LINKS 0
+#endif
+template <typename R> __device__ __forceinline__ void st_out(cpx<R>* p, const cpx<R>& v) {
+    if constexpr (HOP_NT_STORE) {
+        __builtin_nontemporal_store(v.x, &p->x);
+        __builtin_nontemporal_store(v.y, &p->y);
+    } else {
+        *p = v;
+    }
+}
+template <typename T> __device__ __forceinline__ void st_raw(T* p, const T& v) {
+    if constexpr (HOP_NT_STORE) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <typename R> __device__ __forceinline__ cpx<R> ld_link(const cpx<R>* p) {
+    if constexpr (HOP_NT_LINKS) return cpx<R>{__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+    else return *p;
+}
+
+// ---- FP16 storage of a Krylov half field (EOFA_MIXED_FP16): per (cb, s) column the 12 complex
+// components as binary16 (re, im) pairs in 3 blocks of 4 (16 bytes, one load per block):
+// F[cb][jb < 3][Ns][4 pairs], each column scaled by its own FP32 norm = the largest |real component| of
+// its 24 reals, stored after the 12 Vh Ns pairs.  value = norm * half, |half| <= 1.
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 
 template <int NS> __device__ __forceinline__ const float* h_norms(const void* f, int Vh) {
-    return (const float*)((const h2_t*)f + (size_t)12 * Vh * NS);
+    return (const float*)((const h8_t*)f + (size_t)3 * Vh * NS);
 }
 
 template <int NS>
 __device__ __forceinline__ void load_h(cpx<float> p[12], const void* __restrict__ f, size_t cb, int s, int Vh) {
-    const h2_t* d = (const h2_t*)f + cb * 12 * NS + s;
+    const h8_t* d = (const h8_t*)f + cb * 3 * NS + s;
     const float n = h_norms<NS>(f, Vh)[cb * NS + s];
 #pragma unroll
-    for (int j = 0; j < 12; j++) {
-        const h2_t v = d[j * NS];
-        p[j] = {n * (float)v.x, n * (float)v.y};
+    for (int jb = 0; jb < 3; jb++) {
+        const h8_t v = d[jb * NS];
+#pragma unroll
+        for (int k = 0; k < 4; k++) p[4 * jb + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
     }
 }
 
@@ -48,15 +75,18 @@ __device__ __forceinline__ void store_h(void* __restrict__ f, size_t cb, int s, 
 #pragma unroll
     for (int j = 0; j < 12; j++) m = fmaxf(m, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
     const float inv = m > 0.0f ? 1.0f / m : 0.0f;
-    h2_t* d = (h2_t*)f + cb * 12 * NS + s;
+    h8_t* d = (h8_t*)f + cb * 3 * NS + s;
 #pragma unroll
-    for (int j = 0; j < 12; j++) {
-        h2_t h;
-        h.x = (_Float16)(v[j].x * inv);
-        h.y = (_Float16)(v[j].y * inv);
-        d[j * NS] = h;
+    for (int jb = 0; jb < 3; jb++) {
+        h8_t h;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            h[2 * k] = (_Float16)(v[4 * jb + k].x * inv);
+            h[2 * k + 1] = (_Float16)(v[4 * jb + k].y * inv);
+        }
+        st_raw(d + jb * NS, h);
     }
-    ((float*)h_norms<NS>(f, Vh))[cb * NS + s] = m;
+    st_raw((float*)h_norms<NS>(f, Vh) + cb * NS + s, m);
 }
 
 // 12 components of (cb, s) from a field in storage H (FP16 columns) or plain cpx<R>
@@ -78,7 +108,7 @@ __device__ __forceinline__ void store_col(void* __restrict__ f, size_t cb, int s
     } else {
         cpx<R>* dst = (cpx<R>*)f + cb * 12 * NS + s;
 #pragma unroll
-        for (int j = 0; j < 12; j++) dst[j * NS] = v[j];
+        for (int j = 0; j < 12; j++) st_out(dst + j * NS, v[j]);
     }
 }
 
@@ -160,7 +190,7 @@ __device__ __forceinline__ void stage_links(cpx<R> (*sU)[8][9], const cpx<R>* __
         const int l = e / 9, k = e % 9;
         const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k
                                     : Uoth + ((size_t)nb[2 * (l - 4) + 1] * 4 + (l - 4)) * 9 + k;
-        sU[ls][l][k] = *src;
+        sU[ls][l][k] = ld_link(src);
     }
     __syncthreads();
 }
@@ -307,7 +337,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
     }
     if (valid) {
 #pragma unroll
-        for (int j = 0; j < 12; j++) a.out[base + j * NS] = v[j];
+        for (int j = 0; j < 12; j++) st_out(a.out + base + j * NS, v[j]);
     }
     if constexpr (MODE == HM_SCHUR_W) {
         if constexpr (RED) {
@@ -317,7 +347,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
         site_op<NS, true>(v, *a.opB, s, lane);
         if (valid) {
 #pragma unroll
-            for (int j = 0; j < 12; j++) a.out2[base + j * NS] = v[j];
+            for (int j = 0; j < 12; j++) st_out(a.out2 + base + j * NS, v[j]);
         }
     } else if constexpr (RED) {
 #pragma unroll
