@@ -17,7 +17,8 @@ hipError_t cnn_conv_fwd(const unsigned short* X, const unsigned short* W, const 
 int cnn_wgrad_chunks(int rows);
 hipError_t cnn_wgrad(const unsigned short* dYT, const unsigned short* XT, float* part, float* gw, const Geom& g, int Ns,
                      int cin, int cout, hipStream_t st);
-hipError_t cnn_bgrad(const float* dY, int rows, float* gb, int cout, hipStream_t st);
+// part: scratch of >= 256 x 32 doubles
+hipError_t cnn_bgrad(const float* dY, int rows, float* gb, int cout, double* part, hipStream_t st);
 hipError_t cnn_to_chmajor(const void* in, bool in_f32, unsigned short* out, int rows, hipStream_t st);
 hipError_t cnn_f32_to_bf16(const float* in, unsigned short* out, size_t n, hipStream_t st);
 hipError_t cnn_relu_bwd(float* d, const unsigned short* act, size_t n, hipStream_t st);

@@ -113,6 +113,146 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const unsigned short* __restri
         }
 }
 
+// -------------------------------------------------------------------- forward conv, LDS-tiled
+// A workgroup (2 waves) owns a 4 x 4 x 2 x 2 block of compressed sites (xh, y, z, t) and 2 s-slices
+// = 128 rows.  It stages the block with its one-site halo (6 x 6 x 4 x 4 sites x 2 slices x 64 B =
+// 72 KB) in LDS once, then every tap reads its A operands from LDS: global traffic is the halo
+// (9x the block) instead of one gathered row block per tap (81x).  Needs Lxh % 4 == 0, Ly % 4 == 0,
+// Lz, Lt, Ns even.
+constexpr int CT_X = 4, CT_Y = 4, CT_Z = 2, CT_T = 2, CT_S = 2;
+constexpr int CH_X = CT_X + 2, CH_Y = CT_Y + 2, CH_Z = CT_Z + 2, CH_T = CT_T + 2;
+constexpr int CH_SITES = CH_X * CH_Y * CH_Z * CH_T;  // 576
+constexpr int CT_ROWS = CT_X * CT_Y * CT_Z * CT_T * CT_S;  // 128
+
+template <bool OUT_F32>
+__global__ __launch_bounds__(128) void k_conv_fwd_lds(const unsigned short* __restrict__ X,
+                                                      const unsigned short* __restrict__ W,
+                                                      const float* __restrict__ bias, void* __restrict__ Y, CbGeom g,
+                                                      int relu) {
+    // 16-byte units: [halo site][slice][4 k-blocks]
+    __shared__ uint4 lds[CH_SITES * CT_S * 4];
+    const int nbx = g.Lxh / CT_X, nby = g.Ly / CT_Y, nbz = g.Lz / CT_Z, nbt = g.Lt / CT_T;
+    int b = blockIdx.x;
+    const int bx = b % nbx; b /= nbx;
+    const int by = b % nby; b /= nby;
+    const int bz = b % nbz; b /= nbz;
+    const int bt = b % nbt; b /= nbt;
+    const int s0 = b * CT_S;
+    const int x0 = bx * CT_X, y0 = by * CT_Y, z0 = bz * CT_Z, t0 = bt * CT_T;
+    // stage: halo site h -> its 2 rows (128 contiguous bytes) = 8 chunks of 16 B; 36 chunks per thread,
+    // loaded in batches of 12 independent loads (wrap by compare, no integer division by the extents)
+    auto wrap = [](int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); };
+    constexpr int PER = CH_SITES * 8 / 128, BATCH = 12;
+    static_assert(PER % BATCH == 0, "staging batches");
+#pragma unroll
+    for (int i0 = 0; i0 < PER; i0 += BATCH) {
+        uint4 v[BATCH];
+#pragma unroll
+        for (int i = 0; i < BATCH; i++) {
+            const int c = threadIdx.x + 128 * (i0 + i);
+            int h = c >> 3;
+            const int part = c & 7;
+            const int hx = h % CH_X; h /= CH_X;
+            const int hy = h % CH_Y; h /= CH_Y;
+            const int hz = h % CH_Z;
+            const int ht = h / CH_Z;
+            const int gx = wrap(x0 + hx - 1, g.Lxh), gy = wrap(y0 + hy - 1, g.Ly);
+            const int gz = wrap(z0 + hz - 1, g.Lz), gt = wrap(t0 + ht - 1, g.Lt);
+            const size_t cb = (size_t)gx + (size_t)g.Lxh * (gy + (size_t)g.Ly * (gz + (size_t)g.Lz * gt));
+            v[i] = *(const uint4*)(X + (cb * g.Ns + s0) * 32 + part * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < BATCH; i++) lds[threadIdx.x + 128 * (i0 + i)] = v[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int li = lane & 15, kb = lane >> 4;
+    // tile rows: r = site * 2 + slice, site = ((lt * CT_Z + lz) * CT_Y + ly) * CT_X + lx; wave w owns rows [64w, 64w+64)
+    int abase[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        const int r = wave * 64 + t * 16 + li;
+        const int sl = r & 1;
+        int site = r >> 1;
+        const int lx = site % CT_X; site /= CT_X;
+        const int ly = site % CT_Y; site /= CT_Y;
+        const int lz = site % CT_Z;
+        const int lt = site / CT_Z;
+        const int hs = (lx + 1) + CH_X * ((ly + 1) + CH_Y * ((lz + 1) + CH_Z * (lt + 1)));
+        abase[t] = (hs * CT_S + sl) * 4 + kb;
+    }
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        acc[t][0] = {0, 0, 0, 0};
+        acc[t][1] = {0, 0, 0, 0};
+    }
+    // the weights of the next (dt, dz, dy) group of 3 taps are in flight while this group computes
+    const unsigned short* wl = W + li * 32 + kb * 8;
+    bf16x8 bw[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        bw[d][0] = *(const bf16x8*)(wl + (size_t)d * 1024);
+        bw[d][1] = *(const bf16x8*)(wl + (size_t)d * 1024 + 512);
+    }
+    for (int tq = 0; tq < 27; tq++) {  // (dt, dz, dy) of the tap; dx unrolled
+        const int dy = tq % 3 - 1, dz = (tq / 3) % 3 - 1, dt = tq / 9 - 1;
+        const int off_yzt = CH_X * (dy + CH_Y * (dz + CH_Z * dt));
+        bf16x8 bn[3][2];
+        const int tn = (tq < 26 ? tq + 1 : tq) * 3;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            bn[d][0] = *(const bf16x8*)(wl + (size_t)(tn + d) * 1024);
+            bn[d][1] = *(const bf16x8*)(wl + (size_t)(tn + d) * 1024 + 512);
+        }
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++) {
+            const int off = (off_yzt + dx) * CT_S * 4;
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const uint4 raw = lds[abase[t] + off];
+                const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
+                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dx + 1][0], acc[t][0], 0, 0, 0);
+                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dx + 1][1], acc[t][1], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            bw[d][0] = bn[d][0];
+            bw[d][1] = bn[d][1];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int n = h * 16 + li;
+            const float bn = bias ? bias[n] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int r = wave * 64 + t * 16 + kb * 4 + j;
+                const int sl = r & 1;
+                int site = r >> 1;
+                const int lx = site % CT_X; site /= CT_X;
+                const int ly = site % CT_Y; site /= CT_Y;
+                const int lz = site % CT_Z;
+                const int lt = site / CT_Z;
+                const size_t cb = (size_t)(x0 + lx) +
+                                  (size_t)g.Lxh * ((y0 + ly) + (size_t)g.Ly * ((z0 + lz) + (size_t)g.Lz * (t0 + lt)));
+                const size_t row = cb * g.Ns + s0 + sl;
+                float v = acc[t][h][j] + bn;
+                if (relu && v < 0.0f) v = 0.0f;
+                if constexpr (OUT_F32) ((float*)Y)[row * 32 + n] = v;
+                else ((unsigned short*)Y)[row * 32 + n] = bf16_bits(v);
+            }
+        }
+}
+
+static bool conv_tiles(const CbGeom& g) {
+    return g.Lxh % CT_X == 0 && g.Ly % CT_Y == 0 && g.Lz % CT_Z == 0 && g.Lt % CT_T == 0 && g.Ns % CT_S == 0;
+}
+
 // -------------------------------------------------------------------- weight gradient
 // dW[tap][n][k] = sum_rows dY[row][n] X[nbr(row, tap)][k], from channel-major dYT [32][rows] and
 // XT [32][rows] (bf16).  Block (chunk, tap): 4 waves = the four 16x16 tiles of the 32x32 block,
@@ -150,6 +290,92 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const unsigned short* __rest
     for (int j = 0; j < 4; j++) dst[(nt * 16 + kb * 4 + j) * 32 + kt * 16 + li] = acc[j];
 }
 
+// Same weight gradient with more reuse: block (chunk, tq) computes the three taps (dt, dz, dy) = tq,
+// dx = -1, 0, 1, each wave the full 32 x 32 of all three over a quarter of the chunk's rows (one dY
+// operand pair feeds 12 MFMAs), then the four waves' sums are added in LDS in a fixed order.
+__global__ __launch_bounds__(256) void k_conv_wgrad3(const unsigned short* __restrict__ dYT,
+                                                     const unsigned short* __restrict__ XT, float* __restrict__ part,
+                                                     CbGeom g, int rows, int chunk_rows) {
+    const int tq = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, kb = lane >> 4;
+    const int dy = tq % 3 - 1, dz = (tq / 3) % 3 - 1, dt = tq / 9 - 1;
+    f32x4 acc[3][2][2];  // [dx][n tile][k tile]
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            acc[a][b][0] = {0, 0, 0, 0};
+            acc[a][b][1] = {0, 0, 0, 0};
+        }
+    const int quarter = chunk_rows / 4;  // multiple of 32
+    const int r_begin = chunk * chunk_rows + w * quarter;
+    const int r_end = min(rows, r_begin + quarter);
+    const int sy = g.Lxh, sz = g.Lxh * g.Ly, st = sz * g.Lz;
+    for (int rb = r_begin; rb < r_end; rb += 32) {
+        const int r8 = rb + kb * 8;  // 8 rows (one site, 8 consecutive s) of this lane's k block
+        bf16x8 a0, a1, b[3][2];
+        if (r8 + 8 <= r_end) {
+            a0 = *(const bf16x8*)(dYT + (size_t)li * rows + r8);
+            a1 = *(const bf16x8*)(dYT + (size_t)(16 + li) * rows + r8);
+            const int cb = r8 / g.Ns, sl = r8 - cb * g.Ns;
+            int xh = cb % g.Lxh, q = cb / g.Lxh;
+            const int y = q % g.Ly; q /= g.Ly;
+            const int z = q % g.Lz;
+            const int t = q / g.Lz;
+            const int yzt = ((y + dy + g.Ly) % g.Ly) * sy + ((z + dz + g.Lz) % g.Lz) * sz + ((t + dt + g.Lt) % g.Lt) * st;
+#pragma unroll
+            for (int dx = -1; dx <= 1; dx++) {
+                const int nrow = (yzt + (xh + dx + g.Lxh) % g.Lxh) * g.Ns + sl;
+                b[dx + 1][0] = *(const bf16x8*)(XT + (size_t)li * rows + nrow);
+                b[dx + 1][1] = *(const bf16x8*)(XT + (size_t)(16 + li) * rows + nrow);
+            }
+        } else {
+            for (int j = 0; j < 8; j++) {
+                a0[j] = (__bf16)0.0f; a1[j] = (__bf16)0.0f;
+                for (int d = 0; d < 3; d++) { b[d][0][j] = (__bf16)0.0f; b[d][1][j] = (__bf16)0.0f; }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            acc[d][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[d][0], acc[d][0][0], 0, 0, 0);
+            acc[d][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[d][1], acc[d][0][1], 0, 0, 0);
+            acc[d][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[d][0], acc[d][1][0], 0, 0, 0);
+            acc[d][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[d][1], acc[d][1][1], 0, 0, 0);
+        }
+    }
+    // waves 1..3 park their sums in LDS, wave 0 adds them in order and writes the partial
+    __shared__ float red[3][3 * 1024];
+    if (w > 0) {
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+                for (int kt = 0; kt < 2; kt++)
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        red[w - 1][d * 1024 + (nt * 16 + kb * 4 + j) * 32 + kt * 16 + li] = acc[d][nt][kt][j];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            float* dst = part + ((size_t)chunk * 81 + tq * 3 + d) * 1024;
+#pragma unroll
+            for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+                for (int kt = 0; kt < 2; kt++)
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int e = (nt * 16 + kb * 4 + j) * 32 + kt * 16 + li;
+                        dst[e] = ((acc[d][nt][kt][j] + red[0][d * 1024 + e]) + red[1][d * 1024 + e]) + red[2][d * 1024 + e];
+                    }
+        }
+    }
+}
+
 // sum over chunks (fixed order) -> g[tap][n][k], masked to the live channels
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int nchunk, float* __restrict__ gw,
                                                       int cin, int cout) {
@@ -161,26 +387,54 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ 
     gw[i] = (n < cout && k < cin) ? s : 0.0f;
 }
 
-// bias gradient: gb[n] = sum_rows dY[row][n]  (one block per channel; fixed order)
-__global__ __launch_bounds__(256) void k_bgrad(const float* __restrict__ dY, int rows, float* __restrict__ gb, int cout) {
-    const int n = blockIdx.x;
+// bias gradient gb[n] = sum_rows dY[row][n], in two fixed-order stages: block b sums rows
+// b*8 + (tid/32) + k*8*gridDim into part[b][n] (coalesced: 8 rows x 32 channels per step), then one
+// block adds the partials.
+constexpr int BGRAD_BLOCKS = 256;
+__global__ __launch_bounds__(256) void k_bgrad_part(const float* __restrict__ dY, int rows, double* __restrict__ part) {
+    const int n = threadIdx.x & 31, r0 = threadIdx.x >> 5;
     double s = 0.0;
-    for (int r = threadIdx.x; r < rows; r += 256) s += dY[(size_t)r * 32 + n];
-    __shared__ double lds[4];
-    s = block_sum256(s, lds);
-    if (threadIdx.x == 0) gb[n] = (n < cout) ? (float)s : 0.0f;
+    for (size_t r = (size_t)blockIdx.x * 8 + r0; r < (size_t)rows; r += (size_t)8 * gridDim.x) s += dY[r * 32 + n];
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        double t = 0.0;
+        for (int k = 0; k < 8; k++) t += red[k * 32 + n];
+        part[(size_t)blockIdx.x * 32 + n] = t;
+    }
+}
+__global__ __launch_bounds__(32) void k_bgrad_fin(const double* __restrict__ part, int nb, float* __restrict__ gb, int cout) {
+    const int n = threadIdx.x;
+    double t = 0.0;
+    for (int b = 0; b < nb; b++) t += part[(size_t)b * 32 + n];
+    gb[n] = (n < cout) ? (float)t : 0.0f;
 }
 
 // -------------------------------------------------------------------- elementwise helpers
-// [rows][32] (bf16 or f32) -> channel-major [32][rows] bf16
+// [rows][32] (bf16 or f32) -> channel-major [32][rows] bf16, through a 64-row LDS tile (reads and writes
+// both coalesced)
 template <bool IN_F32>
 __global__ __launch_bounds__(256) void k_to_chmajor(const void* __restrict__ in, unsigned short* __restrict__ out, int rows) {
-    const size_t n = (size_t)rows * 32;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        const int c = (int)(i / rows);
-        const size_t r = i % rows;
-        float v = IN_F32 ? ((const float*)in)[r * 32 + c] : bf16_float(((const unsigned short*)in)[r * 32 + c]);
-        out[i] = bf16_bits(v);
+    __shared__ unsigned short tile[32][64 + 2];
+    const size_t r0 = (size_t)blockIdx.x * 64;
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int e = threadIdx.x + 256 * k;  // 2048 elements: row e / 32, channel e % 32
+        const int rr = e >> 5, c = e & 31;
+        const size_t r = r0 + rr;
+        float v = 0.0f;
+        if (r < (size_t)rows)
+            v = IN_F32 ? ((const float*)in)[r * 32 + c] : bf16_float(((const unsigned short*)in)[r * 32 + c]);
+        tile[c][rr] = bf16_bits(v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+        const int e = threadIdx.x + 256 * k;  // channel e / 64, row e % 64
+        const int c = e >> 6, rr = e & 63;
+        const size_t r = r0 + rr;
+        if (r < (size_t)rows) out[(size_t)c * rows + r] = tile[c][rr];
     }
 }
 
@@ -290,8 +544,22 @@ static inline int grid_for(size_t n) {
 
 static CbGeom cbg(const Geom& g, int Ns) { return CbGeom{g.Lxh, g.Ly, g.Lz, g.Lt, Ns, g.Vh}; }
 
+#ifndef CNN_CONV_LDS
+#define CNN_CONV_LDS 1
+#endif
+#ifndef CNN_WGRAD3
+#define CNN_WGRAD3 1
+#endif
+
 hipError_t cnn_conv_fwd(const unsigned short* X, const unsigned short* W, const float* bias, void* Y, bool out_f32,
                         const Geom& g, int Ns, int relu, hipStream_t st) {
+    const CbGeom cg = cbg(g, Ns);
+    if (CNN_CONV_LDS && conv_tiles(cg)) {
+        const int nblk = g.Vh * Ns / CT_ROWS;
+        if (out_f32) hipLaunchKernelGGL(k_conv_fwd_lds<true>, dim3(nblk), dim3(128), 0, st, X, W, bias, Y, cg, relu);
+        else hipLaunchKernelGGL(k_conv_fwd_lds<false>, dim3(nblk), dim3(128), 0, st, X, W, bias, Y, cg, relu);
+        return hipGetLastError();
+    }
     const int rows = g.Vh * Ns;
     const int waves = (rows + 63) / 64;
     const int grid = (waves + 3) / 4;
@@ -305,8 +573,14 @@ hipError_t cnn_wgrad(const unsigned short* dYT, const unsigned short* XT, float*
     const int rows = g.Vh * Ns;
     const int nchunk = cnn_wgrad_chunks(rows);
     const int chunk_rows = (rows + nchunk - 1) / nchunk;
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunk, 81), dim3(256), 0, st, dYT, XT, part, cbg(g, Ns), rows,
-                       (chunk_rows + 31) / 32 * 32);
+    if (CNN_WGRAD3) {
+        // each of the 4 waves takes a quarter of the chunk: chunk rows a multiple of 128
+        hipLaunchKernelGGL(k_conv_wgrad3, dim3(nchunk, 27), dim3(256), 0, st, dYT, XT, part, cbg(g, Ns), rows,
+                           (chunk_rows + 127) / 128 * 128);
+    } else {
+        hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunk, 81), dim3(256), 0, st, dYT, XT, part, cbg(g, Ns), rows,
+                           (chunk_rows + 31) / 32 * 32);
+    }
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((81 * 1024 + 255) / 256), dim3(256), 0, st, part, nchunk, gw, cin, cout);
     return hipGetLastError();
 }
@@ -316,14 +590,16 @@ int cnn_wgrad_chunks(int rows) {
     return c < 1 ? 1 : (c > 256 ? 256 : c);
 }
 
-hipError_t cnn_bgrad(const float* dY, int rows, float* gb, int cout, hipStream_t st) {
-    hipLaunchKernelGGL(k_bgrad, dim3(32), dim3(256), 0, st, dY, rows, gb, cout);
+hipError_t cnn_bgrad(const float* dY, int rows, float* gb, int cout, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(k_bgrad_part, dim3(BGRAD_BLOCKS), dim3(256), 0, st, dY, rows, part);
+    hipLaunchKernelGGL(k_bgrad_fin, dim3(1), dim3(32), 0, st, part, BGRAD_BLOCKS, gb, cout);
     return hipGetLastError();
 }
 
 hipError_t cnn_to_chmajor(const void* in, bool in_f32, unsigned short* out, int rows, hipStream_t st) {
-    if (in_f32) hipLaunchKernelGGL(k_to_chmajor<true>, dim3(grid_for((size_t)rows * 32)), dim3(256), 0, st, in, out, rows);
-    else hipLaunchKernelGGL(k_to_chmajor<false>, dim3(grid_for((size_t)rows * 32)), dim3(256), 0, st, in, out, rows);
+    const int g = (rows + 63) / 64;
+    if (in_f32) hipLaunchKernelGGL(k_to_chmajor<true>, dim3(g), dim3(256), 0, st, in, out, rows);
+    else hipLaunchKernelGGL(k_to_chmajor<false>, dim3(g), dim3(256), 0, st, in, out, rows);
     return hipGetLastError();
 }
 

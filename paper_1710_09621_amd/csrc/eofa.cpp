@@ -622,7 +622,7 @@ double cnn_grad(eofa_ctx* ctx, const cd* rho, const cd* e) {
         HIPCHK(cnn_to_chmajor(dcur, true, c.dYT, rows, ctx->st));
         HIPCHK(cnn_to_chmajor(in, false, c.XT, rows, ctx->st));
         HIPCHK(cnn_wgrad(c.dYT, c.XT, c.part, c.G + (size_t)l * CNN_LSZ, ctx->g, ctx->Ns, CNN_CIN[l], CNN_COUT[l], ctx->st));
-        HIPCHK(cnn_bgrad(dcur, rows, c.G + (size_t)l * CNN_LSZ + CNN_WSZ, CNN_COUT[l], ctx->st));
+        HIPCHK(cnn_bgrad(dcur, rows, c.G + (size_t)l * CNN_LSZ + CNN_WSZ, CNN_COUT[l], (double*)c.part, ctx->st));
         if (l > 0) {
             HIPCHK(cnn_f32_to_bf16(dcur, c.dYb, r32, ctx->st));
             HIPCHK(cnn_conv_fwd(c.dYb, c.Wt + (size_t)l * CNN_WSZ, nullptr, c.dA, true, ctx->g, ctx->Ns, 0, ctx->st));

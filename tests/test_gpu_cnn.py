@@ -18,7 +18,8 @@ pytestmark = pytest.mark.gpu
 TOL_BF16_REF = 1e-2
 TOL_F32_REF = 4e-2
 
-CASES = [((6, 4, 4, 4), 8), ((4, 4, 4, 4), 16)]
+# the first two lattices run the gathered kernel, the last two the LDS-tiled one (Lxh % 4 == 0, Ly % 4 == 0)
+CASES = [((6, 4, 4, 4), 8), ((4, 4, 4, 4), 16), ((8, 4, 4, 4), 8), ((8, 8, 4, 2), 16)]
 
 
 def _odd(dims):
@@ -50,8 +51,9 @@ def test_forward_matches_reference(dims, Ns, relu):
 
 
 @pytest.mark.parametrize("relu", [False, True])
-def test_loss_and_weight_gradient_match_reference(relu):
-    dims, Ns = (4, 4, 4, 4), 8
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 4)], ids=lambda d: "x".join(map(str, d)))
+def test_loss_and_weight_gradient_match_reference(dims, relu):
+    Ns = 8
     print(f"[gpu] cnn gradient dims={dims} Ns={Ns} relu={relu}", flush=True)
     ctx, lat = ctx_and_oracle(dims, Ns)
     p = IN.cnn_params(13, scale=1.5)
