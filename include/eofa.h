@@ -46,7 +46,7 @@ typedef struct eofa_ctx eofa_ctx;
 
 typedef enum {
     EOFA_OK = 0,
-    EOFA_EINVAL = -1,   /* bad argument (message says which) */
+    EOFA_EINVAL = -1,   /* bad argument (message says which), including a source with NaN/Inf */
     EOFA_ENOMEM = -2,   /* device allocation or workspace too small */
     EOFA_EHIP = -3,     /* a HIP runtime call failed */
     EOFA_ENOCONV = -4,  /* solver hit max_iter or broke down; best iterate returned */
@@ -133,8 +133,8 @@ eofa_status eofa_chiral_action(eofa_ctx *ctx, int chir, double m3, double m4, do
  * n independent chiral actions solved together (the multi-RHS form): action j has chirality
  * chir[j] and masses (m3[j], m4[j], mo[j]) as in eofa_chiral_action, source phi[j] and output
  * out[j] (arrays of n device pointers held in HOST memory).  S[j] (host, may be NULL), info[j].
- * Systems sharing (m3, m4) are batched into one launch sequence; links are loaded once per
- * site for the whole batch.
+ * Up to 8 systems go through each launch sequence, each with its own masses; links are loaded
+ * once per site for the whole group.
  */
 eofa_status eofa_chiral_action_batch(eofa_ctx *ctx, int n, const int *chir, const double *m3,
                                      const double *m4, const double *mo, const void *const *phi,

@@ -854,6 +854,7 @@ void refine(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_sol
 SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
     SolveOut so;
     const double cn2 = norm2_64(ctx, W.c);
+    REQUIRE(std::isfinite(cn2), EOFA_EINVAL, "source has non-finite entries");
     for (int par = 0; par < 2; par++) {
         HIPCHK(hipMemsetAsync(W.x.h[par], 0, ctx->nh * sizeof(cd), ctx->st));
         HIPCHK(hipMemcpyAsync(W.res.h[par], W.c.h[par], ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
@@ -1208,6 +1209,7 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
             y.Ai = site_tab(ctx, SK_AINV, y.mp, y.mm);
             y.Ad = site_tab(ctx, SK_AINV_DAG, y.mp, y.mm);
             make_source(ctx, W, chir[j], phi[j]);
+            REQUIRE(std::isfinite(norm2_64(ctx, W.c)), EOFA_EINVAL, "source has non-finite entries");
             prep_schur(ctx, W, y.Ai, y.bh);
         }
         const double tol_n = 0.25 * P->tol;

@@ -1,0 +1,93 @@
+"""Degenerate inputs and error paths of the C ABI on the GPU (all forced from the host side)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import ctx_and_oracle, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    print("[gpu] edge cases dims=(4, 4, 4, 4) Ns=8", flush=True)
+    return ctx_and_oracle((4, 4, 4, 4), 8)
+
+
+def _phi(lat, seed):
+    rng = np.random.default_rng(seed)
+    return torch.as_tensor(rng.standard_normal(lat.shape4) + 1j * rng.standard_normal(lat.shape4))
+
+
+def test_zero_source_gives_zero(setup):
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    for prec in (E.FP64, E.MIXED_FP32, E.MIXED_FP16):
+        r = ctx.hinv(torch.zeros(lat.shape4, dtype=torch.complex128), 0.05, 1.0, E.params(prec=prec))
+        assert r.S == 0.0 and bool((r.out == 0).all())
+
+
+def test_equal_masses_give_identity(setup):
+    """H^{-1}(m, m) = 1: both chiral parts carry k = 0."""
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    phi = _phi(lat, 41)
+    r = ctx.hinv(phi, 0.3, 0.3, E.params())
+    assert relerr(r.out, phi.numpy()) < 1e-14
+    assert abs(r.S - float((phi.abs() ** 2).sum())) <= 1e-12 * r.S
+
+
+def test_max_iter_reports_noconv(setup):
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    with pytest.raises(E.EofaError) as ei:
+        ctx.chiral_action(-1, 0.01, 0.01, 1.0, _phi(lat, 42), E.params(max_iter=3))
+    assert ei.value.status == E.ENOCONV
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_non_finite_source_is_rejected(setup, batch):
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    phi = _phi(lat, 43)
+    phi[1, 2, 3, 0, 2, 1] = float("nan")
+    with pytest.raises(E.EofaError) as ei:
+        if batch:
+            ctx.chiral_action_batch([(-1, 0.05, 0.05, 1.0), (1, 0.05, 1.0, 1.0)], [phi, phi], E.params())
+        else:
+            ctx.chiral_action(-1, 0.05, 0.05, 1.0, phi, E.params())
+    assert ei.value.status == E.EINVAL and "non-finite" in str(ei.value)
+    # the context stays usable
+    r = ctx.hinv(_phi(lat, 44), 0.05, 1.0, E.params())
+    assert np.isfinite(r.S)
+
+
+@pytest.mark.parametrize("bad", [dict(tol=0.0), dict(max_iter=0), dict(prec=7), dict(pc=5)])
+def test_bad_params_are_einval(setup, bad):
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    with pytest.raises(E.EofaError) as ei:
+        ctx.hinv(_phi(lat, 45), 0.05, 1.0, E.params(**bad))
+    assert ei.value.status == E.EINVAL
+
+
+@pytest.mark.parametrize("masses", [(0.0, 0.5), (0.5, 1.5), (-0.1, 0.5)])
+def test_bad_masses_are_einval(setup, masses):
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    with pytest.raises(E.EofaError) as ei:
+        ctx.chiral_action(-1, masses[0], masses[1], 1.0, _phi(lat, 46), E.params())
+    assert ei.value.status == E.EINVAL
+
+
+def test_nine_systems_span_two_groups(setup):
+    """9 actions = one group of 8 plus one of 1 in the multi-RHS path; each equals its single solve."""
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    acts = [(-1, 0.01, 0.01, 0.1), (1, 0.01, 0.1, 1.0), (-1, 1.0, 0.1, 1.0)] * 3
+    phis = [_phi(lat, 50 + j) for j in range(9)]
+    for prec in (E.MIXED_FP32, E.MIXED_FP16):
+        rb = ctx.chiral_action_batch(acts, phis, E.params(tol=1e-11, prec=prec))
+        for a, phi, b in zip(acts, phis, rb):
+            rs = ctx.chiral_action(*a, phi, E.params(tol=1e-11))
+            assert relerr(b.out, rs.out.cpu().numpy()) < 1e-8
