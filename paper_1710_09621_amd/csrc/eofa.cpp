@@ -505,6 +505,7 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
     HIPCHK(launch_convert_d2f(W.r, F.r, nh, ctx->st));
     HIPCHK(hipMemcpyAsync(F.p, F.r, nh * sizeof(cpx<float>), hipMemcpyDeviceToDevice, ctx->st));
     HIPCHK(hipMemsetAsync(F.x, 0, nh * sizeof(cpx<float>), ctx->st));
+    int stall = 0;
     while (o.iters < maxit) {
         // inner FP32 iterations until |r|^2 <= max(delta^2, target) * rr (the last replaced residual)
         const double tol2 = std::max(delta * delta, tol_n * tol_n * rr0 / rr);
@@ -536,11 +537,15 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
         // reliable update: x_hi += x_lo ; r = Dhat^dag (bh - Dhat x_hi) in FP64
         HIPCHK(launch_accum_f(W.xcg, F.x, nh, ctx->st));
         HIPCHK(hipMemsetAsync(F.x, 0, nh * sizeof(cpx<float>), ctx->st));
+        const double rr_prev = rr;
         rr = normal_residual64(ctx, W, W.xcg, W.bh, Ai, Ad);
         o.applies += 2;
         if (updates) (*updates)++;
         if (!std::isfinite(rr)) { ctx->err = "mixed CG: non-finite residual"; return o; }
         if (rr <= tol_n * tol_n * rr0) { o.converged = true; return o; }
+        // stagnation (less than 2x in norm over 8 replacements): hand back to the FP64 defect correction
+        stall = (rr > 0.25 * rr_prev) ? stall + 1 : 0;
+        if (stall >= 8) return o;
         HIPCHK(launch_convert_d2f(W.r, F.r, nh, ctx->st));
     }
     return o;
@@ -834,20 +839,27 @@ void refine(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_sol
             SolveOut& so) {
     const int ce = auto_check_every(ctx, P);
     so.relres = rel;
+    eofa_solve_params Q = P;  // switched to plain FP64 CG if a correction fails to halve the defect
     for (int attempt = 0; attempt < 20; attempt++) {
         if (rel <= P.tol) { so.ok = true; return; }
         if (so.iters >= P.max_iter) return;
         if (attempt > 0) so.restarts++;
         // inner target on the normal residual, relative to the current defect
         double tol_n = std::max(0.25 * P.tol / rel, 1e-15);
-        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce, P, &so.updates,
+        CgOut o = eo_correct64(ctx, W, mp, mm, std::min(tol_n, 0.5), P.max_iter - so.iters, ce, Q, &so.updates,
                                &so.fell_back);
         so.iters += o.iters;
         so.applies += o.applies;
         double r2 = residual64(ctx, W, mp, mm);
+        const double prev = rel;
         rel = std::sqrt(r2 / cn2);
         so.relres = rel;
         if (!std::isfinite(rel)) { ctx->err = "non-finite residual"; return; }
+        if (rel > 0.5 * prev && (Q.prec != EOFA_FP64 || Q.pc != EOFA_PC_NONE)) {
+            Q.prec = EOFA_FP64;
+            Q.pc = EOFA_PC_NONE;
+            so.fell_back = 1;
+        }
     }
 }
 
@@ -866,6 +878,8 @@ SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, con
 
 // ------------------------------------------------------------------ multi-RHS batch
 struct Sys {
+    int stall = 0;      // consecutive reliable updates that failed to halve the residual norm
+    double rr_last = 0; // |r|^2 at the last reliable update
     double mp = 0, mm = 0;
     const SiteOp* Ai = nullptr;
     const SiteOp* Ad = nullptr;
@@ -1026,7 +1040,11 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
             HIPCHK(hipMemsetAsync(y.x, 0, nb, ctx->st));
             double rr = normal_residual64(ctx, W, y.xhi, y.bh, y.Ai, y.Ad);
             y.updates++;
-            if (rr <= tol_n * tol_n * y.rr0 || !std::isfinite(rr)) {
+            // stagnation: the reduced-precision iteration no longer reduces the FP64 residual (the
+            // defect correction above the batch then continues in FP64)
+            y.stall = (y.rr_last > 0 && rr > 0.25 * y.rr_last) ? y.stall + 1 : 0;
+            y.rr_last = rr;
+            if (rr <= tol_n * tol_n * y.rr0 || !std::isfinite(rr) || y.stall >= 8) {
                 y.conv = true;
                 HIPCHK(launch_scal_set(sys_scal(ctx, r), SC_DONE, 1.0, SC_DONEX, 1.0, -1, 0, ctx->st));
                 continue;

@@ -91,3 +91,18 @@ def test_nine_systems_span_two_groups(setup):
         for a, phi, b in zip(acts, phis, rb):
             rs = ctx.chiral_action(*a, phi, E.params(tol=1e-11))
             assert relerr(b.out, rs.out.cpu().numpy()) < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["MIXED_FP32", "MIXED_FP16"])
+def test_frequent_replacement_still_converges(setup, prec):
+    """reliable_delta = 0.99 replaces the residual after every 1% of progress: the solve must still
+    reach the FP64 residual (oracle check)."""
+    from paper_1710_09621_amd import eofa as E
+    from gpu_common import rand5
+    ctx, lat = setup
+    b = torch.as_tensor(rand5(lat, 47))
+    x, info = ctx.solve_ht(b, 0.05, 1.0, E.params(tol=1e-10, prec=getattr(E, prec), reliable_delta=0.99))
+    print(f"  {prec}: {info}")
+    assert info["true_rel_resid"] <= 1e-10
+    r = lat.ht(x.cpu().numpy(), 0.05, 1.0) - b.numpy()
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b.numpy())
