@@ -72,7 +72,7 @@ typedef struct {
     int iters;             /* inner Krylov iterations */
     int op_applies;        /* applications of the even-odd operator Dhat (or its adjoint) */
     int reliable_updates;  /* FP64 residual recomputations (restarts included) */
-    int fell_back;         /* learned-preconditioner solve fell back to CG */
+    int fell_back;         /* the learned-preconditioner or reduced-precision solve handed over to FP64 CG */
     double true_rel_resid; /* FP64 ||b - H_T x|| / ||b|| of the returned x */
     double seconds;        /* wall time of the solve */
 } eofa_solve_info;
