@@ -255,42 +255,9 @@ static bool conv_tiles(const CbGeom& g) {
 
 // -------------------------------------------------------------------- weight gradient
 // dW[tap][n][k] = sum_rows dY[row][n] X[nbr(row, tap)][k], from channel-major dYT [32][rows] and
-// XT [32][rows] (bf16).  Block (chunk, tap): 4 waves = the four 16x16 tiles of the 32x32 block,
-// reduction over the rows of the chunk in steps of 32 (8 consecutive rows share one site since
-// Ns % 8 == 0).  Partials go to part[chunk][tap][32][32].
-__global__ __launch_bounds__(256) void k_conv_wgrad(const unsigned short* __restrict__ dYT,
-                                                    const unsigned short* __restrict__ XT, float* __restrict__ part,
-                                                    CbGeom g, int rows, int chunk_rows) {
-    const int tap = blockIdx.y;
-    const int chunk = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nt = w >> 1, kt = w & 1;  // output tile (n block, k block)
-    const int li = lane & 15, kb = lane >> 4;
-    f32x4 acc = {0, 0, 0, 0};
-    const int r_begin = chunk * chunk_rows;
-    const int r_end = min(rows, r_begin + chunk_rows);
-    for (int rb = r_begin; rb < r_end; rb += 32) {
-        const int r8 = rb + kb * 8;  // 8 rows of this lane's k block
-        bf16x8 a, b;
-        if (r8 + 8 <= r_end) {
-            a = *(const bf16x8*)(dYT + (size_t)(nt * 16 + li) * rows + r8);
-            const int cb = r8 / g.Ns, s = r8 - cb * g.Ns;
-            int off[4][3];
-            cb_offsets(g, cb, off);
-            const int nrow = tap_cb(off, tap) * g.Ns + s;
-            b = *(const bf16x8*)(XT + (size_t)(kt * 16 + li) * rows + nrow);
-        } else {
-            for (int j = 0; j < 8; j++) { a[j] = (__bf16)0.0f; b[j] = (__bf16)0.0f; }
-        }
-        // A = dY^T tile (n x rows), B = X tile (rows x k): D[n][k]
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    }
-    float* dst = part + ((size_t)chunk * 81 + tap) * 1024;
-#pragma unroll
-    for (int j = 0; j < 4; j++) dst[(nt * 16 + kb * 4 + j) * 32 + kt * 16 + li] = acc[j];
-}
-
-// Same weight gradient with more reuse: block (chunk, tq) computes the three taps (dt, dz, dy) = tq,
+// XT [32][rows] (bf16), so that 8 consecutive rows of one channel (one site, 8 consecutive s when
+// Ns % 8 == 0) are one 16-byte operand.  Partials go to part[chunk][tap][32][32].
+// Block (chunk, tq) computes the three taps (dt, dz, dy) = tq,
 // dx = -1, 0, 1, each wave the full 32 x 32 of all three over a quarter of the chunk's rows (one dY
 // operand pair feeds 12 MFMAs), then the four waves' sums are added in LDS in a fixed order.
 __global__ __launch_bounds__(256) void k_conv_wgrad3(const unsigned short* __restrict__ dYT,
@@ -544,17 +511,11 @@ static inline int grid_for(size_t n) {
 
 static CbGeom cbg(const Geom& g, int Ns) { return CbGeom{g.Lxh, g.Ly, g.Lz, g.Lt, Ns, g.Vh}; }
 
-#ifndef CNN_CONV_LDS
-#define CNN_CONV_LDS 1
-#endif
-#ifndef CNN_WGRAD3
-#define CNN_WGRAD3 1
-#endif
 
 hipError_t cnn_conv_fwd(const unsigned short* X, const unsigned short* W, const float* bias, void* Y, bool out_f32,
                         const Geom& g, int Ns, int relu, hipStream_t st) {
     const CbGeom cg = cbg(g, Ns);
-    if (CNN_CONV_LDS && conv_tiles(cg)) {
+    if (conv_tiles(cg)) {
         const int nblk = g.Vh * Ns / CT_ROWS;
         if (out_f32) hipLaunchKernelGGL(k_conv_fwd_lds<true>, dim3(nblk), dim3(128), 0, st, X, W, bias, Y, cg, relu);
         else hipLaunchKernelGGL(k_conv_fwd_lds<false>, dim3(nblk), dim3(128), 0, st, X, W, bias, Y, cg, relu);
@@ -573,14 +534,9 @@ hipError_t cnn_wgrad(const unsigned short* dYT, const unsigned short* XT, float*
     const int rows = g.Vh * Ns;
     const int nchunk = cnn_wgrad_chunks(rows);
     const int chunk_rows = (rows + nchunk - 1) / nchunk;
-    if (CNN_WGRAD3) {
-        // each of the 4 waves takes a quarter of the chunk: chunk rows a multiple of 128
-        hipLaunchKernelGGL(k_conv_wgrad3, dim3(nchunk, 27), dim3(256), 0, st, dYT, XT, part, cbg(g, Ns), rows,
-                           (chunk_rows + 127) / 128 * 128);
-    } else {
-        hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunk, 81), dim3(256), 0, st, dYT, XT, part, cbg(g, Ns), rows,
-                           (chunk_rows + 31) / 32 * 32);
-    }
+    // each of the 4 waves takes a quarter of the chunk: chunk rows a multiple of 128
+    hipLaunchKernelGGL(k_conv_wgrad3, dim3(nchunk, 27), dim3(256), 0, st, dYT, XT, part, cbg(g, Ns), rows,
+                       (chunk_rows + 127) / 128 * 128);
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((81 * 1024 + 255) / 256), dim3(256), 0, st, part, nchunk, gw, cin, cout);
     return hipGetLastError();
 }

@@ -22,13 +22,10 @@ namespace eofa {
 #define HOP_LDS_LINKS 1
 #endif
 
-// Cache policy of the hop's streams: the outputs are not read again by the same launch and the links
-// are read once per workgroup, so both may bypass the caches that hold the re-read neighbour spinors.
+// Cache policy of the hop's outputs: they are not read again by the same launch, so they bypass the
+// caches that hold the re-read neighbour spinors.
 #ifndef HOP_NT_STORE
 #define HOP_NT_STORE 1
-#endif
-#ifndef HOP_NT_LINKS
-#define HOP_NT_LINKS 0
 #endif
 template <typename R> __device__ __forceinline__ void st_out(cpx<R>* p, const cpx<R>& v) {
     if constexpr (HOP_NT_STORE) {
@@ -41,10 +38,6 @@ template <typename R> __device__ __forceinline__ void st_out(cpx<R>* p, const cp
 template <typename T> __device__ __forceinline__ void st_raw(T* p, const T& v) {
     if constexpr (HOP_NT_STORE) __builtin_nontemporal_store(v, p);
     else *p = v;
-}
-template <typename R> __device__ __forceinline__ cpx<R> ld_link(const cpx<R>* p) {
-    if constexpr (HOP_NT_LINKS) return cpx<R>{__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
-    else return *p;
 }
 
 // ---- FP16 storage of a Krylov half field (EOFA_MIXED_FP16): per (cb, s) column the 12 complex
@@ -141,44 +134,6 @@ __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict_
     }
 }
 
-#ifndef HOP_PIPE
-#define HOP_PIPE 0
-#endif
-
-// Neighbour n of the hop (n = 2 mu + 0 forward, 2 mu + 1 backward) on an already loaded spinor p.
-template <bool DAG, int N, typename R>
-__device__ __forceinline__ void hop_term(cpx<R> acc[12], const cpx<R> p[12], const cpx<R>* Ul) {
-    constexpr int MU = N / 2;
-    constexpr bool FWD = (N % 2) == 0;
-    constexpr int S = FWD ? (DAG ? +1 : -1) : (DAG ? -1 : +1);
-    cpx<R> h[6], w[6], U[9];
-    project<MU, S>(p, h);
-#pragma unroll
-    for (int k = 0; k < 9; k++) U[k] = Ul[k];
-    link_mul<!FWD>(U, h, w);
-    reconstruct<MU, S>(acc, w);
-}
-
-template <int NS, typename R>
-__device__ __forceinline__ void load_spinor(cpx<R> p[12], const cpx<R>* __restrict__ in, int n, int s) {
-    const cpx<R>* src = in + (size_t)n * 12 * NS + s;
-#pragma unroll
-    for (int j = 0; j < 12; j++) p[j] = src[j * NS];
-}
-
-// Software-pipelined walk over the 8 neighbours: the spinor of neighbour n+1 is in flight while
-// neighbour n is multiplied.  Link of neighbour n: sU[n/2] (forward) or sU[4 + n/2] (backward).
-template <int NS, bool DAG, int N, typename R>
-__device__ __forceinline__ void hop_pipe(cpx<R> acc[12], cpx<R> cur[12], const cpx<R>* __restrict__ in,
-                                         const cpx<R> (*sU)[9], const int nb[8], int s) {
-    if constexpr (N < 8) {
-        cpx<R> nxt[12];
-        if constexpr (N < 7) load_spinor<NS>(nxt, in, nb[N + 1], s);
-        hop_term<DAG, N>(acc, cur, sU[(N % 2 == 0) ? N / 2 : 4 + N / 2]);
-        if constexpr (N < 7) hop_pipe<NS, DAG, N + 1>(acc, nxt, in, sU, nb, s);
-    }
-}
-
 // The 8 links of each of the workgroup's 256/NS sites, staged in LDS: sU[site][l][k], l = 0..3 the
 // forward links U_mu(x), l = 4..7 the backward links U_mu(x - mu).  Each entry is read once from
 // global memory instead of once per slice.  Ends with a workgroup barrier.
@@ -190,7 +145,7 @@ __device__ __forceinline__ void stage_links(cpx<R> (*sU)[8][9], const cpx<R>* __
         const int l = e / 9, k = e % 9;
         const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k
                                     : Uoth + ((size_t)nb[2 * (l - 4) + 1] * 4 + (l - 4)) * 9 + k;
-        sU[ls][l][k] = ld_link(src);
+        sU[ls][l][k] = *src;
     }
     __syncthreads();
 }
@@ -209,10 +164,6 @@ __device__ __forceinline__ void hop_lds(cpx<R> z[12], const cpx<R>* __restrict__
         hop_mu<NS, DAG, 2, R, H>(z, in, sUl[2], sUl[6], nb, s, Vh);
         HOP_FENCE();
         hop_mu<NS, DAG, 3, R, H>(z, in, sUl[3], sUl[7], nb, s, Vh);
-    } else if constexpr (HOP_PIPE) {
-        cpx<R> cur[12];
-        load_spinor<NS>(cur, in, nb[0], s);
-        hop_pipe<NS, DAG, 0>(z, cur, in, sUl, nb, s);
     } else {
         hop_mu<NS, DAG, 0>(z, in, sUl[0], sUl[4], nb, s);
         HOP_FENCE();
