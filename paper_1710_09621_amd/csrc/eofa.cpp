@@ -485,6 +485,11 @@ double normal_residual64(eofa_ctx* ctx, const Work64& W, const cd* x, const cd* 
     return ctx->hscal[SC_TMP + 11];
 }
 
+// A replacement cycle that runs this long without reaching its delta target is cut short: the FP64
+// residual is recomputed anyway, so a reduced-precision recurrence that has stopped tracking the true
+// residual is caught by the stagnation test instead of iterating to max_iter.
+constexpr int kMaxCycle = 500;
+
 // Reliable-update CG: FP32 storage and arithmetic for the Krylov iteration, FP64 solution
 // accumulation and FP64 residual replacement whenever |r| has dropped by delta since the
 // last replacement.  Solves Dhat W.xcg = W.bh to |r_normal| <= tol_n |r_normal,0|.
@@ -531,7 +536,7 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
             if (inner % check_every == 0) {
                 sync_scal(ctx);
                 if (!std::isfinite(ctx->hscal[SC_RR])) { ctx->err = "mixed CG breakdown"; return o; }
-                if (ctx->hscal[SC_DONE] != 0.0) break;
+                if (ctx->hscal[SC_DONE] != 0.0 || inner >= kMaxCycle) break;
             }
         }
         // reliable update: x_hi += x_lo ; r = Dhat^dag (bh - Dhat x_hi) in FP64
@@ -878,6 +883,7 @@ SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, con
 
 // ------------------------------------------------------------------ multi-RHS batch
 struct Sys {
+    int cycle = 0;      // iterations since the last residual replacement
     int stall = 0;      // consecutive reliable updates that failed to halve the residual norm
     double rr_last = 0; // |r|^2 at the last reliable update
     double mp = 0, mm = 0;
@@ -1021,21 +1027,22 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
                 for (int k = 0; k < ce; k++) cg_iteration_mr<R, H>(ctx, sys);
             });
             it += ce;
-            for (Sys& y : sys) if (!y.conv) y.iters += ce;
+            for (Sys& y : sys) if (!y.conv) { y.iters += ce; y.cycle += ce; }
         } else {
             cg_iteration_mr<R, H>(ctx, sys);
             it++;
-            for (Sys& y : sys) if (!y.conv) y.iters++;
+            for (Sys& y : sys) if (!y.conv) { y.iters++; y.cycle++; }
         }
         if (it % ce && it < maxit) continue;
         sync_scal_batch(ctx, nr);
         for (int r = 0; r < nr; r++) {
             Sys& y = sys[r];
             const double* hs = ctx->hscal + BATCH_OFF + r * SC_N;
-            if (y.conv || hs[SC_DONE] == 0.0) continue;
+            if (y.conv || (hs[SC_DONE] == 0.0 && !(mixed && y.cycle >= kMaxCycle))) continue;
             if (!std::isfinite(hs[SC_RR])) { ctx->err = "batched CG breakdown"; y.conv = true; continue; }
             if (!mixed) { y.conv = true; HIPCHK(hipMemcpyAsync(y.xhi, y.x, nb, hipMemcpyDeviceToDevice, ctx->st)); continue; }
-            // reliable update of system r
+            // reliable update of system r (its delta target reached, or its cycle cut at kMaxCycle)
+            y.cycle = 0;
             HIPCHK(launch_accum_f(y.xhi, (const cpx<float>*)y.x, ctx->nh, ctx->st));
             HIPCHK(hipMemsetAsync(y.x, 0, nb, ctx->st));
             double rr = normal_residual64(ctx, W, y.xhi, y.bh, y.Ai, y.Ad);
