@@ -168,7 +168,7 @@ size_t batch_sys_bytes(const eofa_ctx* ctx, const eofa_solve_params* p) {
     return 2 * align_up(ctx->nh * sizeof(cd)) + 2 * batch_vec_bytes(ctx, p, true) + 5 * batch_vec_bytes(ctx, p, false);
 }
 
-constexpr int FGCR_M = 8;  // directions kept before a restart
+constexpr int FGCR_M = 8;  // directions kept by the truncated flexible GCR (a ring)
 
 size_t fgcr_bytes(const eofa_ctx* ctx) { return (2 * FGCR_M + 1) * align_up(ctx->nh * sizeof(cd)); }
 
