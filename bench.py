@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HOP_FLOP_PER_SITE = 1320 + 250
 
 
 def log(*a):
@@ -219,7 +220,11 @@ def main():
                      "unit": "GB/s", "frac": round(hop_gbs / HBM_PEAK_GBS, 4) if hop_gbs else None,
                      "traffic": traffic,
                      "kernel": "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)",
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(per_launch_ms, 5)},
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(per_launch_ms, 5),
+                     # 1320 flop per site and slice for the Wilson hop + 250 for the A_T^{-1} epilogue
+                     "flop_per_launch": HOP_FLOP_PER_SITE * Vh * Ns,
+                     "fp64_tflops": round(HOP_FLOP_PER_SITE * Vh * Ns / (per_launch_ms * 1e-3) / 1e12, 3)
+                     if hop_gbs else None},
         "tts": {"plain_fp64_s_per_step": round(tp / args.steps, 3), "plain_iters": iters,
                 "tuned_s_per_step": round(tt / args.steps, 3), "tuned_iters": iters_t,
                 "tuned": f"multi-RHS batch (all systems of the step in one launch sequence), {args.tuned_prec.upper()}-storage "

@@ -71,3 +71,22 @@ def test_full_solve_oracle_residual(full, prec):
     rel = np.linalg.norm(r) / np.linalg.norm(bh)
     print(f"  oracle residual {rel:.2e}")
     assert rel <= 2e-10
+
+
+def test_full_schur_operator(full):
+    """Dhat = 1 - A^{-1} H_oe A^{-1} H_eo / 4 on the odd sites: the benchmarked hop kernel (u =
+    A_T^{-1} H_eo p, autotuned schedule) and its Schur partner, element by element on the whole
+    lattice against the oracle's own Schur operator."""
+    from oracle import oracle as O
+    ctx, lat = full
+    print("[gpu] full size Schur operator", flush=True)
+    x = _gauss5(ctx, 64)
+    y = ctx.apply("SCHUR", x, 0.01, 0.1).cpu().numpy()
+    xh = x.cpu().numpy()
+    del x
+    odd = O.parity_mask(DIMS)
+    xh[:, ~odd] = 0
+    ref = lat.schur(xh, 0.01, 0.1)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"  max rel err {err:.2e}")
+    assert err < 1e-12
