@@ -196,31 +196,41 @@ __global__ __launch_bounds__(128) void k_conv_fwd_lds(const unsigned short* __re
         bw[d][0] = *(const bf16x8*)(wl + (size_t)d * 1024);
         bw[d][1] = *(const bf16x8*)(wl + (size_t)d * 1024 + 512);
     }
-    for (int tq = 0; tq < 27; tq++) {  // (dt, dz, dy) of the tap; dx unrolled
+    // A fragments of a (dt, dz, dy) group of 3 taps: [dx][row tile]; the next group's are read from LDS
+    // while this group's 24 MFMAs run
+    auto load_group = [&](int tq, uint4 (*a)[4]) {
         const int dy = tq % 3 - 1, dz = (tq / 3) % 3 - 1, dt = tq / 9 - 1;
         const int off_yzt = CH_X * (dy + CH_Y * (dz + CH_Z * dt));
+#pragma unroll
+        for (int dx = -1; dx <= 1; dx++)
+#pragma unroll
+            for (int t = 0; t < 4; t++) a[dx + 1][t] = lds[abase[t] + (off_yzt + dx) * CT_S * 4];
+    };
+    uint4 acur[3][4], anext[3][4];
+    load_group(0, acur);
+    for (int tq = 0; tq < 27; tq++) {
         bf16x8 bn[3][2];
-        const int tn = (tq < 26 ? tq + 1 : tq) * 3;
+        const int tn = (tq < 26 ? tq + 1 : tq);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            bn[d][0] = *(const bf16x8*)(wl + (size_t)(tn + d) * 1024);
-            bn[d][1] = *(const bf16x8*)(wl + (size_t)(tn + d) * 1024 + 512);
+            bn[d][0] = *(const bf16x8*)(wl + (size_t)(3 * tn + d) * 1024);
+            bn[d][1] = *(const bf16x8*)(wl + (size_t)(3 * tn + d) * 1024 + 512);
         }
+        load_group(tn, anext);
 #pragma unroll
-        for (int dx = -1; dx <= 1; dx++) {
-            const int off = (off_yzt + dx) * CT_S * 4;
+        for (int d = 0; d < 3; d++)
 #pragma unroll
             for (int t = 0; t < 4; t++) {
-                const uint4 raw = lds[abase[t] + off];
-                const bf16x8 a = __builtin_bit_cast(bf16x8, raw);
-                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dx + 1][0], acc[t][0], 0, 0, 0);
-                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[dx + 1][1], acc[t][1], 0, 0, 0);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, acur[d][t]);
+                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[d][0], acc[t][0], 0, 0, 0);
+                acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[d][1], acc[t][1], 0, 0, 0);
             }
-        }
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             bw[d][0] = bn[d][0];
             bw[d][1] = bn[d][1];
+#pragma unroll
+            for (int t = 0; t < 4; t++) acur[d][t] = anext[d][t];
         }
     }
 #pragma unroll

@@ -18,8 +18,9 @@ pytestmark = pytest.mark.gpu
 TOL_BF16_REF = 1e-2
 TOL_F32_REF = 4e-2
 
-# the first two lattices run the gathered kernel, the last two the LDS-tiled one (Lxh % 4 == 0, Ly % 4 == 0)
-CASES = [((6, 4, 4, 4), 8), ((4, 4, 4, 4), 16), ((8, 4, 4, 4), 8), ((8, 8, 4, 2), 16)]
+# the first two lattices run the gathered kernel, the others the LDS-tiled one (Lxh % 4 == 0, Ly % 4 == 0):
+# 4 x 4 x 2 x 2 site blocks when Lz = 2, 4 x 4 x 4 x 2 blocks when Lz % 4 == 0
+CASES = [((6, 4, 4, 4), 8), ((4, 4, 4, 4), 16), ((8, 4, 2, 4), 8), ((8, 4, 4, 4), 8), ((8, 8, 4, 2), 16)]
 
 
 def _odd(dims):
@@ -51,7 +52,7 @@ def test_forward_matches_reference(dims, Ns, relu):
 
 
 @pytest.mark.parametrize("relu", [False, True])
-@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 4, 4)], ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (8, 4, 2, 4), (8, 4, 4, 4)], ids=lambda d: "x".join(map(str, d)))
 def test_loss_and_weight_gradient_match_reference(dims, relu):
     Ns = 8
     print(f"[gpu] cnn gradient dims={dims} Ns={Ns} relu={relu}", flush=True)
