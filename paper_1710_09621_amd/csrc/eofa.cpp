@@ -1323,7 +1323,7 @@ void fill_bench_buffers(eofa_ctx* ctx) {
     HIPCHK(hipMemsetAsync(W.u, 0x3F, ctx->nh * sizeof(cd), ctx->st));
 }
 
-std::vector<Sched> sched_candidates(const eofa_ctx* ctx) {
+std::vector<Sched> sched_candidates(const eofa_ctx* ctx, int prec) {
     std::vector<Sched> c;
     const Geom& g = ctx->g;
     const long lanes_line = (long)g.Lxh * g.Ly * ctx->Ns;  // lanes of one (z, t) line
@@ -1351,6 +1351,21 @@ std::vector<Sched> sched_candidates(const eofa_ctx* ctx) {
                     if (pz < 4 || pz > 64) continue;
                     c.push_back(Sched{1, x, ty, tz, tt, nyb, 1});
                 }
+    }
+    if (prec != EOFA_MIXED_FP16) {
+        // t-walk: patches of 8 .. 64 segments per XCD, chunks of 16 slabs or the whole t extent, with
+        // and without 48 KB of reserved LDS (one workgroup per CU)
+        for (int ty : opts)
+            for (int tz : opts)
+                for (int tt : {16, g.Lt})
+                    for (int pad : {0, 48}) {
+                        const Sched s{3, 1, ty, tz, tt, nyb, pad};
+                        const int per = ty * tz;
+                        if (per < 8 || per > 64 || tw_grid(g, ctx->Ns, s) == 0) continue;
+                        bool dup = false;
+                        for (const Sched& o : c) dup |= (o.mode == 3 && o.ty == ty && o.tz == tz && o.tt == tt && o.ord == pad);
+                        if (!dup) c.push_back(s);
+                    }
     }
     return c;
 }
@@ -1668,7 +1683,7 @@ eofa_status eofa_autotune(eofa_ctx* ctx, int prec, int nrep, int sched_out[7], d
         if (prec == EOFA_MIXED_FP16) ensure_partials_mr(ctx);
         fill_bench_buffers(ctx);
         const int k = prec;
-        std::vector<Sched> cand = sched_candidates(ctx);
+        std::vector<Sched> cand = sched_candidates(ctx, prec);
         double best = 1e30, base = 0;
         Sched bs = cand[0];
         for (size_t i = 0; i < cand.size(); i++) {
@@ -1695,7 +1710,7 @@ eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[7]) {
                 "prec must be FP64, MIXED_FP32 or MIXED_FP16");
         Sched s{sched_in[0], sched_in[1], sched_in[2], sched_in[3], sched_in[4], sched_in[5], sched_in[6]};
         bool ok = false;
-        for (const Sched& c : sched_candidates(ctx))
+        for (const Sched& c : sched_candidates(ctx, prec))
             ok |= (c.mode == s.mode && c.xcd == s.xcd && c.ty == s.ty && c.tz == s.tz && c.tt == s.tt &&
                    c.nyb == s.nyb && c.ord == s.ord);
         REQUIRE(ok, EOFA_EINVAL, "schedule not valid for this lattice");

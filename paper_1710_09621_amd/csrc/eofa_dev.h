@@ -91,8 +91,52 @@ struct ChirTab {
 // One site-local operator = tables for the upper (P+) and lower (P-) spin halves.
 struct SiteOp { ChirTab h[2]; };
 
-template <int NS, int SIG, int K, typename R>
-__device__ __forceinline__ void ring_scan_step(cpx<R> v[6], const ChirTab& t, int s, int lane) {
+// A copy of the first NS entries of a ChirTab / SiteOp, staged by a workgroup in LDS (stage_siteop).
+template <int NS> struct ChirTabL {
+    double pre[NS];
+    double mid[NS];
+    double shf[NS];
+    double post[NS];
+    double q[ilog2(NS) > 0 ? ilog2(NS) : 1][NS];
+};
+template <int NS> struct SiteOpL { ChirTabL<NS> h[2]; };
+
+// Staging of a SiteOp into LDS by a workgroup of 256 lanes, in two halves so that the caller can issue
+// other loads between them: siteop_fetch loads this lane's share into registers, siteop_store writes it
+// to d (published by the caller's next workgroup barrier).
+template <int NS> struct SiteOpShare {
+    static constexpr int L = ilog2(NS) > 0 ? ilog2(NS) : 1;
+    static constexpr int F = 4 + L, TOT = 2 * F * NS, NQ = (TOT + 255) / 256;
+    double v[NQ];
+};
+
+template <int NS>
+__device__ __forceinline__ void siteop_fetch(SiteOpShare<NS>& sh, const SiteOp& op) {
+    using S = SiteOpShare<NS>;
+#pragma unroll
+    for (int k = 0; k < S::NQ; k++) {
+        const int e = min((int)threadIdx.x + 256 * k, S::TOT - 1);  // lanes past the end repeat the last entry
+        const int hf = e / (S::F * NS), f = (e / NS) % S::F, si = e % NS;
+        const double* row = f == 0 ? op.h[hf].pre : f == 1 ? op.h[hf].mid : f == 2 ? op.h[hf].shf
+                          : f == 3 ? op.h[hf].post : op.h[hf].q[f - 4];
+        sh.v[k] = row[si];
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ void siteop_store(SiteOpL<NS>& d, const SiteOpShare<NS>& sh) {
+    using S = SiteOpShare<NS>;
+    static_assert(sizeof(ChirTabL<NS>) == sizeof(double) * S::F * NS, "ChirTabL layout");
+    double* flat = &d.h[0].pre[0];  // h[hf] rows pre, mid, shf, post, q[0..L) are contiguous
+#pragma unroll
+    for (int k = 0; k < S::NQ; k++) {
+        const int e = threadIdx.x + 256 * k;
+        if (e < S::TOT) flat[e] = sh.v[k];
+    }
+}
+
+template <int NS, int SIG, int K, typename R, typename T>
+__device__ __forceinline__ void ring_scan_step(cpx<R> v[6], const T& t, int s, int lane) {
     if constexpr (K < ilog2(NS)) {
         const R qk = (R)t.q[K][s];
         constexpr int OFF = SIG * (1 << K);
@@ -107,8 +151,8 @@ __device__ __forceinline__ void ring_scan_step(cpx<R> v[6], const ChirTab& t, in
 }
 
 // ORDER 0: solve then shift (A^{-1}-type ops).  ORDER 1: shift then solve (their transposes).
-template <int NS, int SIG, int ORDER, typename R>
-__device__ __forceinline__ void chir_op(cpx<R> v[6], const ChirTab& t, int s, int lane) {
+template <int NS, int SIG, int ORDER, typename R, typename T>
+__device__ __forceinline__ void chir_op(cpx<R> v[6], const T& t, int s, int lane) {
     const R pre = (R)t.pre[s], post = (R)t.post[s], shf = (R)t.shf[s];
 #pragma unroll
     for (int j = 0; j < 6; j++) v[j] = cscale(pre, v[j]);
@@ -136,8 +180,8 @@ __device__ __forceinline__ void chir_op(cpx<R> v[6], const ChirTab& t, int s, in
 
 // Apply a site-local operator to a 12-component spinor held lane-wise over s.
 // DAG = false: upper half couples s to s-1 (L_+), lower to s+1 (L_-); DAG = true reverses both.
-template <int NS, bool DAG, typename R>
-__device__ __forceinline__ void site_op(cpx<R> v[12], const SiteOp& op, int s, int lane) {
+template <int NS, bool DAG, typename R, typename Op>
+__device__ __forceinline__ void site_op(cpx<R> v[12], const Op& op, int s, int lane) {
     constexpr int SU = DAG ? +1 : -1;
     constexpr int ORD = DAG ? 1 : 0;
     chir_op<NS, SU, ORD>(v, op.h[0], s, lane);

@@ -14,6 +14,10 @@ enum : int { HM_LIN = 0, HM_SITE = 1, HM_SCHUR_W = 2, HM_SCHUR_Q = 3, HM_DT = 4,
 // ty x tz x tt workgroups visited tile by tile.  xcd != 0: every XCD (the 8 L2 domains) gets
 // one contiguous range of the visiting sequence instead of every 8th workgroup.
 // ord = 1 visits each tile with its (z, t) plane fastest and yb slowest.
+// mode 3 (single-system FP64 / FP32 hop only): t-walk.  A workgroup owns one segment of 256 / Ns
+// sites of a t-slab and walks tt consecutive slabs; the segments form an nyb x (segments / nyb) grid
+// and the workgroups that run together on an XCD take a ty x tz patch of it; ord = KB of LDS reserved
+// per workgroup (caps the workgroups per CU).  The other kernels read mode 3 as mode 0.
 struct Sched {
     int mode, xcd, ty, tz, tt, nyb, ord;
 };
@@ -76,6 +80,7 @@ template <typename R> hipError_t launch_cg_xp_mr(int nr, cpx<R>* const* x, cpx<R
                                                  double* scal, size_t n, hipStream_t st);
 
 template <typename R> hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st);
+int tw_grid(const Geom& g, int Ns, const Sched& sc);
 template <typename R> hipError_t launch_site(int Ns, bool dag, const cpx<R>* in, cpx<R>* out, const SiteOp* op, int Vh,
                                              hipStream_t st);
 template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, const double* scal, size_t n,

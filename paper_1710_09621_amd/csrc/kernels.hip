@@ -137,15 +137,35 @@ __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict_
 // The 8 links of each of the workgroup's 256/NS sites, staged in LDS: sU[site][l][k], l = 0..3 the
 // forward links U_mu(x), l = 4..7 the backward links U_mu(x - mu).  Each entry is read once from
 // global memory instead of once per slice.  Ends with a workgroup barrier.
-template <int NS, typename R>
+struct NoStore {
+    __device__ void operator()() const {}
+};
+// between issuing its loads and writing LDS it runs more_stores (LDS writes of other staged data whose
+// loads were issued before, so that one memory round trip covers both).
+// TW: slot 7 holds U_t of the input site x + t instead of U_t(x - t) (the t-walk's carry link).
+template <int NS, typename R, typename F = NoStore, bool TW = false>
 __device__ __forceinline__ void stage_links(cpx<R> (*sU)[8][9], const cpx<R>* __restrict__ Uown,
-                                            const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s) {
+                                            const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s,
+                                            F more_stores = F()) {
     const int ls = threadIdx.x / NS;
-    for (int e = s; e < 72; e += NS) {
-        const int l = e / 9, k = e % 9;
-        const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k
-                                    : Uoth + ((size_t)nb[2 * (l - 4) + 1] * 4 + (l - 4)) * 9 + k;
-        sU[ls][l][k] = *src;
+    constexpr int NQ = (72 + NS - 1) / NS;
+    // complex entries moved as 2-vectors: whole-struct copies through a private array are lowered to
+    // memcpy, which can keep the array in scratch memory
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {  // every load in flight before the first LDS write; no branches
+        const int e = min(s + q * NS, 71), l = e / 9, k = e % 9;
+        // selects, not nb[2 * (l - 4) + 1]: a runtime index would move nb out of registers
+        const int nbl = l == 4 ? nb[1] : l == 5 ? nb[3] : l == 6 ? nb[5] : (TW ? nb[6] : nb[7]);
+        const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k : Uoth + ((size_t)nbl * 4 + (l - 4)) * 9 + k;
+        v[q] = *(const v2*)src;
+    }
+    more_stores();
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        const int e = s + q * NS;
+        if (e < 72) *(v2*)&sU[ls][e / 9][e % 9] = v[q];
     }
     __syncthreads();
 }
@@ -176,14 +196,18 @@ __device__ __forceinline__ void hop_lds(cpx<R> z[12], const cpx<R>* __restrict__
 }
 
 // z = hop(in) at (cb, s).  With HOP_LDS_LINKS the workgroup first stages its sites' links in LDS.
-template <int NS, bool DAG, typename R>
+// more_stores runs once before the workgroup barrier that publishes the staged data.
+template <int NS, bool DAG, typename R, typename F>
 __device__ __forceinline__ void hop_all(cpx<R> z[12], const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ Uown,
-                                        const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s) {
+                                        const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s,
+                                        F more_stores) {
     if constexpr (HOP_LDS_LINKS && NS >= 8) {
         __shared__ cpx<R> sU[256 / NS][8][9];
-        stage_links<NS>(sU, Uown, Uoth, cb, nb, s);
+        stage_links<NS>(sU, Uown, Uoth, cb, nb, s, more_stores);
         hop_lds<NS, DAG>(z, in, sU[threadIdx.x / NS], nb, s);
     } else {
+        more_stores();
+        __syncthreads();
 #pragma unroll
         for (int j = 0; j < 12; j++) z[j] = {0, 0};
         hop_mu<NS, DAG, 0>(z, in, Uown + ((size_t)cb * 4 + 0) * 9, Uoth + ((size_t)nb[1] * 4 + 0) * 9, nb, s);
@@ -231,20 +255,12 @@ __device__ __forceinline__ int tile_of(int b, int n, const Sched& sc, const Geom
 #define HOP_WAVES 2
 #endif
 
-template <int NS, bool DAG, int MODE, bool RED, typename R>
-__global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
-    if (a.done && *a.done != 0.0) return;
-    const int tid = tile_of(blockIdx.x, gridDim.x, a.sc, a.g) * 256 + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int s = lane & (NS - 1);
-    int cb = tid / NS;
-    const bool valid = cb < a.g.Vh;
-    if (!valid) cb = a.g.Vh - 1;  // keep every lane of a group active for the lane exchanges
-    int nb[8];
-    neighbours(a.g, cb, a.par, nb);
-    cpx<R> z[12];
-    hop_all<NS, DAG>(z, a.in, a.Uown, a.Uoth, cb, nb, s);
-
+// The epilogue of the fused hop at (cb, s) given z = hop(in): stores out (and out2 for HM_SCHUR_W) when
+// valid and returns this lane's contribution to the reduced norm (0 unless RED).  opA / opB are the
+// site-local operators (LDS copies).
+template <int NS, bool DAG, int MODE, bool RED, typename R, typename TA, typename TB>
+__device__ __forceinline__ double hop_epilogue(const HopArgs<R>& a, cpx<R> z[12], int cb, int s, int lane,
+                                               bool valid, const TA& opA, const TB& opB) {
     const size_t base = (size_t)cb * 12 * NS + s;
     double nrm = 0.0;
     cpx<R> v[12];
@@ -252,9 +268,9 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < 12; j++) v[j] = cscale(a.cz, z[j]);
         if (a.aux) add_aux(v, a.aux + base, a.caux);
-        if constexpr (MODE == HM_SITE) site_op<NS, DAG>(v, *a.opA, s, lane);
+        if constexpr (MODE == HM_SITE) site_op<NS, DAG>(v, opA, s, lane);
     } else if constexpr (MODE == HM_SCHUR_W) {
-        site_op<NS, false>(z, *a.opA, s, lane);
+        site_op<NS, false>(z, opA, s, lane);
 #pragma unroll
         for (int j = 0; j < 12; j++) {
             cpx<R> t = a.aux[base + j * NS];
@@ -277,7 +293,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
         cpx<R> m[12];
 #pragma unroll
         for (int j = 0; j < 12; j++) m[j] = d[j];
-        if constexpr (MODE == HM_DT) site_op<NS, DAG>(m, *a.opA, s, lane);
+        if constexpr (MODE == HM_DT) site_op<NS, DAG>(m, opA, s, lane);
 #pragma unroll
         for (int j = 0; j < 12; j++) {
             R tx = a.diag * d[j].x - (R)0.5 * z[j].x, ty = a.diag * d[j].y - (R)0.5 * z[j].y;
@@ -295,7 +311,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
 #pragma unroll
             for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
         }
-        site_op<NS, true>(v, *a.opB, s, lane);
+        site_op<NS, true>(v, opB, s, lane);
         if (valid) {
 #pragma unroll
             for (int j = 0; j < 12; j++) st_out(a.out2 + base + j * NS, v[j]);
@@ -304,9 +320,157 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
 #pragma unroll
         for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
     }
+    return valid ? nrm : 0.0;
+}
+
+// LDS copies of the site-local operators the epilogue of MODE applies: ops_fetch issues the loads,
+// ops_store writes the copies (published by the next barrier).
+template <int NS> struct OpsShare { SiteOpShare<NS> A, B; };
+template <int NS, int MODE, typename R>
+__device__ __forceinline__ void ops_fetch(OpsShare<NS>& sh, const HopArgs<R>& a) {
+    if constexpr (MODE == HM_SITE || MODE == HM_SCHUR_W || MODE == HM_DT) siteop_fetch<NS>(sh.A, *a.opA);
+    if constexpr (MODE == HM_SCHUR_W) siteop_fetch<NS>(sh.B, *a.opB);
+}
+template <int NS, int MODE>
+__device__ __forceinline__ void ops_store(SiteOpL<NS>& sA, SiteOpL<NS>& sB, const OpsShare<NS>& sh) {
+    if constexpr (MODE == HM_SITE || MODE == HM_SCHUR_W || MODE == HM_DT) siteop_store<NS>(sA, sh.A);
+    if constexpr (MODE == HM_SCHUR_W) siteop_store<NS>(sB, sh.B);
+}
+
+template <int NS, bool DAG, int MODE, bool RED, typename R>
+__global__ __launch_bounds__(256, HOP_WAVES) void k_hop(const HopArgs<R> a) {
+    if (a.done && *a.done != 0.0) return;
+    const int tid = tile_of(blockIdx.x, gridDim.x, a.sc, a.g) * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int s = lane & (NS - 1);
+    int cb = tid / NS;
+    const bool valid = cb < a.g.Vh;
+    if (!valid) cb = a.g.Vh - 1;  // keep every lane of a group active for the lane exchanges
+    int nb[8];
+    neighbours(a.g, cb, a.par, nb);
+    __shared__ SiteOpL<NS> sA, sB;
+    OpsShare<NS> sh;
+    ops_fetch<NS, MODE>(sh, a);
+    cpx<R> z[12];
+    hop_all<NS, DAG>(z, a.in, a.Uown, a.Uoth, cb, nb, s, [&] { ops_store<NS, MODE>(sA, sB, sh); });
+    const double nrm = hop_epilogue<NS, DAG, MODE, RED>(a, z, cb, s, lane, valid, sA, sB);
     if constexpr (RED) {
         __shared__ double lds[4];
-        if (!valid) nrm = 0.0;
+        finish_sum(a.red, block_sum256(nrm, lds));
+    }
+}
+
+// ===================================================================== t-walk form of the hop
+// Workgroup -> (segment, t-chunk) of the t-walk schedule (Sched mode 3).  A segment is 256 / NS
+// consecutive sites of a t-slab; the segments form an nyb x (nseg / nyb) grid (y-like, z-like).  The
+// workgroups that run at the same time on one XCD take one ty x tz patch of that grid.
+__device__ __forceinline__ void tw_tile(int b, int n, const Sched& sc, int nseg, int& seg, int& chunk) {
+    if (sc.xcd) {  // hardware dispatches workgroup b to XCD b % 8
+        const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+        b = x * q + (x < r ? x : r) + i;
+    }
+    const int per = sc.ty * sc.tz, nyb = sc.nyb, nzb = nseg / nyb;
+    const int intra = b % per, tile = b / per;
+    const int npy = nyb / sc.ty, npz = nzb / sc.tz;
+    const int py = tile % npy, pz = (tile / npy) % npz;
+    chunk = tile / (npy * npz);
+    seg = (py * sc.ty + intra % sc.ty) + nyb * (pz * sc.tz + intra / sc.ty);
+}
+
+// The t-neighbours of a site have its slab index, so one lane walks its (segment position, s) through
+// the slabs t0 .. t0 + tt - 1.  The input column of slab t+1 that the forward t term of slab t loads is,
+// projected and multiplied by U_t(x + t)^dag, the backward t term of slab t+2: it is formed once and
+// kept for two steps in a lane-private LDS slot (even and odd slabs).  Links are staged per step in LDS; slot 7 holds
+// the link of the slab-(t+1) input site that the carry needs instead of the backward t link of slab t.
+template <int NS, bool DAG, typename R>
+__device__ __forceinline__ void tw_carry(cpx<R>* cw, const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ Uoth,
+                                         int cbi, int s) {
+    constexpr int SB = DAG ? -1 : +1;
+    cpx<R> p[12], h[6], U[9], w[6];
+    load_col<NS, false>(p, in, (size_t)cbi, s, 0);
+    project<3, SB>(p, h);
+#pragma unroll
+    for (int k = 0; k < 9; k++) U[k] = Uoth[((size_t)cbi * 4 + 3) * 9 + k];
+    link_mul<true>(U, h, w);
+#pragma unroll
+    for (int j = 0; j < 6; j++) cw[j * 256] = w[j];
+}
+
+template <int NS, bool DAG, int MODE, bool RED, typename R>
+__device__ __forceinline__ void tw_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9], const SiteOpL<NS>& sA,
+                                        const SiteOpL<NS>& sB, int cb, int s, int lane, cpx<R>* cw, double& nrm) {
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    const int ls = threadIdx.x / NS;
+    HOP_FENCE();
+    int nb[8];
+    neighbours(a.g, cb, a.par, nb);
+    // the previous step's reads of sU end at the barrier between this step's link loads and LDS writes
+    auto tw_barrier = [] { __syncthreads(); };
+    stage_links<NS, R, decltype(tw_barrier), true>(sU, a.Uown, a.Uoth, cb, nb, s, tw_barrier);
+    cpx<R> z[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) z[j] = {0, 0};
+    hop_mu<NS, DAG, 0>(z, a.in, sU[ls][0], sU[ls][4], nb, s);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 1>(z, a.in, sU[ls][1], sU[ls][5], nb, s);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 2>(z, a.in, sU[ls][2], sU[ls][6], nb, s);
+    HOP_FENCE();
+    {
+        // the slab-(t+1) input column: loaded here rather than a step ahead, since a load in flight across
+        // the next step's link loads would make their wait (an in-order count) wait for it as well
+        cpx<R> p[12], h[6], w[6], U[9];
+        load_col<NS, false>(p, a.in, (size_t)nb[6], s, 0);
+        project<3, SF>(p, h);
+#pragma unroll
+        for (int k = 0; k < 9; k++) U[k] = sU[ls][3][k];
+        link_mul<false>(U, h, w);
+        reconstruct<3, SF>(z, w);
+#pragma unroll
+        for (int j = 0; j < 6; j++) w[j] = cw[j * 256];
+        reconstruct<3, SB>(z, w);  // backward t term, carried from two steps back
+        project<3, SB>(p, h);
+#pragma unroll
+        for (int k = 0; k < 9; k++) U[k] = sU[ls][7][k];
+        link_mul<true>(U, h, w);   // the backward t term of slab t + 2
+#pragma unroll
+        for (int j = 0; j < 6; j++) cw[j * 256] = w[j];
+    }
+    HOP_FENCE();
+    nrm += hop_epilogue<NS, DAG, MODE, RED>(a, z, cb, s, lane, true, sA, sB);
+    HOP_FENCE();
+}
+
+#ifndef HOP_TW_WAVES
+#define HOP_TW_WAVES 1
+#endif
+template <int NS, bool DAG, int MODE, bool RED, typename R>
+__global__ __launch_bounds__(256, HOP_TW_WAVES) void k_hop_tw(const HopArgs<R> a) {
+    if (a.done && *a.done != 0.0) return;
+    __shared__ cpx<R> sU[256 / NS][8][9];
+    __shared__ SiteOpL<NS> sA, sB;
+    {
+        OpsShare<NS> sh;
+        ops_fetch<NS, MODE>(sh, a);
+        ops_store<NS, MODE>(sA, sB, sh);  // published by the first step's barriers
+    }
+    const int nseg = (int)((size_t)a.g.Vh / a.g.Lt * NS / 256);
+    int seg, chunk;
+    tw_tile(blockIdx.x, gridDim.x, a.sc, nseg, seg, chunk);
+    const int lane = threadIdx.x & 63, s = lane & (NS - 1);
+    const int st = a.g.Vh / a.g.Lt;                        // sites per slab
+    const int i = seg * (256 / NS) + threadIdx.x / NS;     // slab index of this lane's site
+    const int TC = a.sc.tt, t0 = chunk * TC;
+    // carried backward t terms, private to each lane: slot t % 2 holds the term of slab t
+    __shared__ cpx<R> carry[2][6][256];
+    tw_carry<NS, DAG>(&carry[0][0][threadIdx.x], a.in, a.Uoth, i + st * (t0 == 0 ? a.g.Lt - 1 : t0 - 1), s);
+    tw_carry<NS, DAG>(&carry[1][0][threadIdx.x], a.in, a.Uoth, i + st * t0, s);
+    double nrm = 0.0;
+    for (int k = 0; k < TC; k++)
+        tw_step<NS, DAG, MODE, RED>(a, sU, sA, sB, i + st * (t0 + k), s, lane, &carry[k & 1][0][threadIdx.x], nrm);
+    if constexpr (RED) {
+        __shared__ double lds[4];
         finish_sum(a.red, block_sum256(nrm, lds));
     }
 }
@@ -786,11 +950,44 @@ hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, 
     default: return hipErrorInvalidValue;                              \
     }
 
+// Whether schedule sc (mode 3) fits the lattice and Ns; the t-walk grid size when it does, else 0.
+int tw_grid(const Geom& g, int Ns, const Sched& sc) {
+    if (sc.mode != 3 || Ns < 8) return 0;
+    const long slab = (long)g.Vh / g.Lt;
+    if ((slab * Ns) % 256 != 0) return 0;
+    const long nseg = slab * Ns / 256;
+    if (sc.tt < 2 || sc.tt % 2 || g.Lt % sc.tt || sc.nyb < 1 || nseg % sc.nyb) return 0;
+    if (sc.ty < 1 || sc.tz < 1 || sc.nyb % sc.ty || (nseg / sc.nyb) % sc.tz) return 0;
+    if (sc.ord < 0 || sc.ord > 64) return 0;  // static LDS of the t-walk is at most 84 KB
+    return (int)(nseg * (g.Lt / sc.tt));
+}
+
+// LDS that a launch of kern may reserve on top of its static LDS (gfx950: 160 KB per workgroup).
+template <typename K> static size_t lds_room(K kern) {
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, (const void*)kern) != hipSuccess) return 0;
+    return at.sharedSizeBytes < 160 * 1024 ? 160 * 1024 - at.sharedSizeBytes : 0;
+}
+
 template <typename R>
 hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st) {
     const size_t nthreads = (size_t)a.g.Vh * Ns;
-    const int grid = (int)((nthreads + 255) / 256);
-#define HOP_L(D, M, RD) hipLaunchKernelGGL((k_hop<NS, D, M, RD, R>), dim3(grid), dim3(256), 0, st, a)
+    const bool tw = a.sc.mode == 3;
+    const int grid = tw ? tw_grid(a.g, Ns, a.sc) : (int)((nthreads + 255) / 256);
+    if (grid <= 0) return hipErrorInvalidValue;
+    const size_t pad = tw ? (size_t)a.sc.ord * 1024 : 0;  // LDS reserved to cap workgroups per CU
+#define HOP_L(D, M, RD)                                                                                  \
+    do {                                                                                                 \
+        if constexpr (NS >= 8) {                                                                         \
+            if (tw) {                                                                                    \
+                static const size_t room = lds_room(k_hop_tw<NS, D, M, RD, R>);                          \
+                hipLaunchKernelGGL((k_hop_tw<NS, D, M, RD, R>), dim3(grid), dim3(256), pad < room ? pad : room, \
+                                   st, a);                                                               \
+                break;                                                                                   \
+            }                                                                                            \
+        }                                                                                                \
+        hipLaunchKernelGGL((k_hop<NS, D, M, RD, R>), dim3(grid), dim3(256), 0, st, a);                  \
+    } while (0)
 #define HOP_MODES(D)                                                                        \
     switch (mode) {                                                                         \
     case HM_LIN: if (red) HOP_L(D, HM_LIN, true); else HOP_L(D, HM_LIN, false); break;     \

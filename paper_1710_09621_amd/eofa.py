@@ -254,6 +254,11 @@ class Context:
         self._check(self.lib.eofa_dslash_bench(self.h, int(prec), int(nrep), C.byref(ms), C.byref(b)), "dslash_bench")
         return dict(ms=ms.value, bytes=b.value, gbs=b.value / (ms.value * 1e-3) / 1e9)
 
+    def set_schedule(self, sched, prec=FP64):
+        """Set the hop schedule (7 ints, as autotune returns them) for storage prec."""
+        arr = (C.c_int * 7)(*[int(v) for v in sched])
+        self._check(self.lib.eofa_set_schedule(self.h, int(prec), arr), "set_schedule")
+
     def autotune(self, prec=FP64, nrep=4, cache=None):
         """Pick the hop schedule for this lattice; cache: JSON path keyed by (dims, Ns, prec, arch)."""
         import json
