@@ -54,9 +54,10 @@ def cpu_baseline(U, dims, Ns, omega, budget_s=12.0):
                       f"{n} applications in {el:.1f} s; bytes per 5D output site as for the GPU hop ({per_site:.0f} B)"}
 
 
-def measured_traffic(path, dims, Ns):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or None
-    when there is none for this lattice or the kernel sources changed since the counters were taken."""
+def measured_traffic(path, dims, Ns, sched):
+    """HBM bytes per launch of the dominant kernel under hop schedule sched, from the committed rocprofv3
+    counter summary, or None when it has no entry for this lattice and schedule or the kernel sources
+    changed since the counters were taken."""
     import hashlib
     if not os.path.exists(path):
         return None
@@ -71,7 +72,11 @@ def measured_traffic(path, dims, Ns):
         if h.hexdigest() != t["source_sha1"] or t["lattice"] != lat or t["Ns"] != Ns:
             log("counter summary is stale (kernel sources or lattice changed): traffic = null")
             return None
-        return round(float(t["bytes_per_launch"]))
+        entry = t["by_schedule"].get(",".join(str(v) for v in sched))
+        if entry is None:
+            log(f"no counter summary for schedule {sched}: traffic = null")
+            return None
+        return round(float(entry["bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
 
@@ -190,7 +195,10 @@ def main():
         f"avg {per_launch_ms:.4f} ms -> {hop_gbs:.1f} GB/s; iters {iters} / {iters_t}; max resid {max(resid):.2e}; "
         f"max |dS|/S {dS:.1e}")
 
-    traffic = measured_traffic(args.traffic, dims, Ns)
+    sched64 = tune["fp64"]["sched"]
+    traffic = measured_traffic(args.traffic, dims, Ns, sched64)
+    kern = ("k_hop_tw<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p; t-walk schedule)" if sched64[0] == 3
+            else "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)")
 
     Vh = int(np.prod(dims)) // 2
     alg_bytes = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)
@@ -219,7 +227,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(hop_gbs, 2) if hop_gbs else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(hop_gbs / HBM_PEAK_GBS, 4) if hop_gbs else None,
                      "traffic": traffic,
-                     "kernel": "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)",
+                     "kernel": kern,
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(per_launch_ms, 5),
                      # 1320 flop per site and slice for the Wilson hop + 250 for the A_T^{-1} epilogue
                      "flop_per_launch": HOP_FLOP_PER_SITE * Vh * Ns,
