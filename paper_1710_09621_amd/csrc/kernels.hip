@@ -547,6 +547,38 @@ __global__ __launch_bounds__(256) void k_finish_mr(const double* __restrict__ pa
     finish_partials(partials + (size_t)blockIdx.x * pstride, n, S, 0, epi);
 }
 
+// x += alpha p ; p = r + beta p on this block's chunk of XP_U * 256 consecutive elements (one launch covers
+// the field, no grid-stride loop): every load of the chunk is issued before the first update, so a thread
+// keeps 3 * XP_U elements in flight instead of 3.
+template <typename R> constexpr int xp_unroll() { return sizeof(R) == 8 ? 4 : 8; }
+template <typename R>
+__device__ __forceinline__ void xp_chunk(cpx<R>* __restrict__ x, cpx<R>* __restrict__ p, const cpx<R>* __restrict__ r,
+                                         R alpha, R beta, size_t n) {
+    constexpr int U = xp_unroll<R>();
+    const size_t i0 = (size_t)blockIdx.x * (256 * U) + threadIdx.x;
+    cpx<R> pp[U], rr[U], xx[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        const size_t i = i0 + (size_t)k * 256;
+        if (i < n) { pp[k] = p[i]; rr[k] = r[i]; xx[k] = x[i]; }
+    }
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        const size_t i = i0 + (size_t)k * 256;
+        if (i < n) {
+            cpx<R> a = xx[k], b = pp[k];
+            a.x = fma(alpha, b.x, a.x); a.y = fma(alpha, b.y, a.y);
+            b.x = fma(beta, b.x, rr[k].x); b.y = fma(beta, b.y, rr[k].y);
+            x[i] = a;
+            p[i] = b;
+        }
+    }
+}
+template <typename R> static inline unsigned xp_grid(size_t n) {
+    const size_t per = (size_t)256 * xp_unroll<R>();
+    return (unsigned)((n + per - 1) / per);
+}
+
 template <typename R> struct XpArgs {
     cpx<R>* x[NRMAX];
     cpx<R>* p[NRMAX];
@@ -558,16 +590,7 @@ __global__ __launch_bounds__(256) void k_cg_xp_mr(const XpArgs<R> a, double* sca
     const int r = blockIdx.y;
     const double* S = scal + r * SC_N;
     if (S[SC_DONEX] != 0.0) return;
-    const R alpha = (R)S[SC_ALPHA], beta = (R)S[SC_BETA];
-    cpx<R>* x = a.x[r];
-    cpx<R>* p = a.p[r];
-    const cpx<R>* rr = a.r[r];
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        cpx<R> pp = p[i], q = rr[i], xx = x[i];
-        xx.x = fma(alpha, pp.x, xx.x); xx.y = fma(alpha, pp.y, xx.y);
-        pp.x = fma(beta, pp.x, q.x);   pp.y = fma(beta, pp.y, q.y);
-        x[i] = xx; p[i] = pp;
-    }
+    xp_chunk<R>(a.x[r], a.p[r], a.r[r], (R)S[SC_ALPHA], (R)S[SC_BETA], n);
 }
 
 // FP16 form: x (FP32) += alpha p ; p (FP16 columns) = r (FP32) + beta p; one thread per (cb, s)
@@ -577,7 +600,8 @@ __global__ __launch_bounds__(256) void k_cg_xp_mr_h(const XpArgs<float> a, doubl
     const double* S = scal + r * SC_N;
     if (S[SC_DONEX] != 0.0) return;
     const float alpha = (float)S[SC_ALPHA], beta = (float)S[SC_BETA];
-    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < (size_t)Vh * NS; t += (size_t)gridDim.x * 256) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;  // one (cb, s) column per thread, no loop
+    if (t < (size_t)Vh * NS) {
         const size_t cb = t / NS;
         const int s = (int)(t % NS);
         cpx<float> p[12], x[12], q[12];
@@ -651,13 +675,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_cg_xp(cpx<R>* __restrict__ x, cpx<R>* __restrict__ p,
                                                const cpx<R>* __restrict__ r, const double* __restrict__ scal,
                                                size_t n) {
-    const R alpha = (R)scal[SC_ALPHA], beta = (R)scal[SC_BETA];
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        cpx<R> pp = p[i], rr = r[i], xx = x[i];
-        xx.x = fma(alpha, pp.x, xx.x); xx.y = fma(alpha, pp.y, xx.y);
-        pp.x = fma(beta, pp.x, rr.x);  pp.y = fma(beta, pp.y, rr.y);
-        x[i] = xx; p[i] = pp;
-    }
+    xp_chunk<R>(x, p, r, (R)scal[SC_ALPHA], (R)scal[SC_BETA], n);
 }
 
 // y = a*x + b*y, with an optional |y|^2 reduction
@@ -1048,7 +1066,7 @@ hipError_t launch_cg_xp_mr_h(int Ns, int nr, cpx<float>* const* x, void* const* 
     if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
     XpArgs<float> a{};
     for (int i = 0; i < nr; i++) { a.x[i] = x[i]; a.p[i] = (cpx<float>*)p[i]; a.r[i] = r[i]; }
-    const int gx = nblk((size_t)Vh * Ns) > 1024 ? 1024 : nblk((size_t)Vh * Ns);
+    const unsigned gx = (unsigned)(((size_t)Vh * Ns + 255) / 256);
     switch (Ns) {
     case 8: hipLaunchKernelGGL((k_cg_xp_mr_h<8>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
     case 16: hipLaunchKernelGGL((k_cg_xp_mr_h<16>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
@@ -1077,8 +1095,7 @@ hipError_t launch_cg_xp_mr(int nr, cpx<R>* const* x, cpx<R>* const* p, cpx<R>* c
     if (nr < 1 || nr > NRMAX) return hipErrorInvalidValue;
     XpArgs<R> a{};
     for (int i = 0; i < nr; i++) { a.x[i] = x[i]; a.p[i] = p[i]; a.r[i] = r[i]; }
-    const int gx = nblk(n) > 1024 ? 1024 : nblk(n);
-    hipLaunchKernelGGL((k_cg_xp_mr<R>), dim3(gx, nr), dim3(256), 0, st, a, scal, n);
+    hipLaunchKernelGGL((k_cg_xp_mr<R>), dim3(xp_grid<R>(n), nr), dim3(256), 0, st, a, scal, n);
     hipLaunchKernelGGL(k_sync_done, dim3(1), dim3(64), 0, st, scal, nr);
     return hipGetLastError();
 }
@@ -1098,7 +1115,7 @@ template hipError_t launch_site<float>(int, bool, const cpx<float>*, cpx<float>*
 
 template <typename R>
 hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, const double* scal, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL((k_cg_xp<R>), dim3(nblk(n)), dim3(256), 0, st, x, p, r, scal, n);
+    hipLaunchKernelGGL((k_cg_xp<R>), dim3(xp_grid<R>(n)), dim3(256), 0, st, x, p, r, scal, n);
     return hipGetLastError();
 }
 template hipError_t launch_cg_xp<double>(cd*, cd*, const cd*, const double*, size_t, hipStream_t);
