@@ -305,6 +305,18 @@ def test_new_mp_telescopes(O, D, tiny):
     assert abs(tot - tot_old) < 1e-9
 
 
+@pytest.mark.parametrize("kind,hs", [("old", [0.05, 0.3]), ("new", [0.05, 0.3]), ("new", [0.03, 0.1, 0.4])])
+def test_mp_cascades_telescope(O, D, tiny, kind, hs):
+    """Eqs.(old_MP_N), (new_MP_N): the actions the splitting generator builds for a cascade of heavy masses
+    have determinants whose product is det D_T(m, m) / det D_T(M, M).  A wrong chirality or mass factor in
+    any one action changes its determinant."""
+    from paper_1710_09621_amd import mpseq
+    L, HT, DT = tiny
+    m, M = 0.01, 1.0
+    tot = sum(D.subspace_logdet(*dense_action(O, D, L, HT, *a))[0] for a in mpseq.actions(kind, m, hs, M))
+    assert abs(-tot - (D.logdet(DT(m, m))[0] - D.logdet(DT(M, M))[0])) < 1e-9
+
+
 def test_overlap_relation(O, D, tiny):
     """Textbook special case: det D_odwf(m) / det D_odwf(1) = det D_ov(m), where D_ov is the
     overlap operator with the Zolotarev-type sign function built from the same omega_s
