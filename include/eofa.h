@@ -130,6 +130,18 @@ eofa_status eofa_chiral_action(eofa_ctx *ctx, int chir, double m3, double m4, do
                                const eofa_solve_params *params, eofa_solve_info *info);
 
 /*
+ * Fermion force of one chiral action (the molecular-dynamics derivative of S above; the force of a
+ * pseudofermion action enters the HMC of Sec. I, and each factor of the splittings of Sec. II has its own):
+ *   force[mu][site][a] = dS/dw^a  for  U_mu(site) -> exp(i w^a T^a) U_mu(site),  T^a = lambda^a / 2,
+ * with mu = 0..3 for x, y, z, t and the site in canonical order (x fastest).  Equals -c k x^dag (dH_T/dw^a) x
+ * with x = H_T(m3,m4)^{-1} Om P_c phi and c = chir.  phi: 4D canonical device buffer; force: caller-owned
+ * device buffer of 4 * V * 8 doubles.  *S as for eofa_chiral_action (may be NULL).  Solves as
+ * eofa_chiral_action does (same params); EOFA_ENOCONV still writes the force of the last iterate.
+ */
+eofa_status eofa_chiral_force(eofa_ctx *ctx, int chir, double m3, double m4, double mo, const void *phi,
+                              double *force, double *S, const eofa_solve_params *params, eofa_solve_info *info);
+
+/*
  * n independent chiral actions solved together (the multi-RHS form): action j has chirality
  * chir[j] and masses (m3[j], m4[j], mo[j]) as in eofa_chiral_action, source phi[j] and output
  * out[j] (arrays of n device pointers held in HOST memory).  S[j] (host, may be NULL), info[j].

@@ -23,6 +23,7 @@
 
 #include "../../include/eofa.h"
 #include "cnn.h"
+#include "force.h"
 #include "eofa_int.h"
 
 using namespace eofa;
@@ -1526,6 +1527,25 @@ eofa_status eofa_set_gauge(eofa_ctx* ctx, const void* U) {
 eofa_status eofa_chiral_action(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, void* out,
                                double* S, const eofa_solve_params* params, eofa_solve_info* info) {
     return guarded(ctx, [&]() { return chiral_impl(ctx, chir, m3, m4, mo, phi, out, 0, S, params, info); });
+}
+
+eofa_status eofa_chiral_force(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, double* force,
+                              double* S, const eofa_solve_params* params, eofa_solve_info* info) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(force, EOFA_EINVAL, "null force pointer");
+        check_params(ctx, params);
+        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+        ensure_ws(ctx, needed_bytes(ctx, params));
+        Work64 W = carve64(ctx);
+        // the 4D output of the action is not needed: a workspace field (written after the solve) takes it
+        eofa_status st = chiral_impl(ctx, chir, m3, m4, mo, phi, (void*)W.res.h[0], 0, S, params, info);
+        if (st != EOFA_OK && st != EOFA_ENOCONV) return st;
+        const double kappa = chir * action_k(chir, m3, m4, mo);
+        for (int par = 0; par < 2; par++)
+            HIPCHK(launch_force(W.x.h[par], W.x.h[1 - par], ctx->U[par], ctx->g, par, ctx->Ns, kappa, force, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        return st;
+    });
 }
 
 eofa_status eofa_hinv(eofa_ctx* ctx, double m_lo, double m_hi, const void* phi, void* out, double* S,

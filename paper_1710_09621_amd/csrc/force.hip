@@ -1,0 +1,119 @@
+// gfx950 kernel of the EOFA fermion force of one chiral action.
+//
+// S = phi^dag P [1 + c k Om^T H_T^{-1} Om] P phi (Sec. II, Eqs.(m1m2_m1m4), (m1m2_m3m2)) depends on the links only
+// through the Wilson hop of D_T.  With x = H_T^{-1} Om P phi and y = gamma_5 R_5 x, the derivative along
+// U_mu(x) -> exp(i w^a T^a) U_mu(x) (T^a = lambda^a / 2) is
+//   dS/dw^a = -(c k / 2) Im Tr[T^a (U B1 - B2 U^dag)],
+//   B1 = sum_s (1 - gamma_mu) x_s(x + mu) (x) y_s(x)^dag,   B2 = sum_s (1 + gamma_mu) x_s(x) (x) y_s(x + mu)^dag,
+// spin-traced colour outer products; the packed links carry the t boundary phase, so U is the link the hop uses.
+#include "force.h"
+
+namespace eofa {
+
+// (1 + sg gamma_mu) p in the chiral basis: upper += sg B_mu lower, lower += sg B_mu^dag upper.
+__device__ __forceinline__ void gamma_apply(cd o[12], const cd p[12], int mu, double sg) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const cd u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
+        cd b0, b1, t0, t1;  // B d and B^dag u
+        switch (mu) {
+        case 0: b0 = cneg(ci(d1)); b1 = cneg(ci(d0)); t0 = ci(u1); t1 = ci(u0); break;
+        case 1: b0 = cneg(d1); b1 = d0; t0 = u1; t1 = cneg(u0); break;
+        case 2: b0 = cneg(ci(d0)); b1 = ci(d1); t0 = ci(u0); t1 = cneg(ci(u1)); break;
+        default: b0 = d0; b1 = d1; t0 = u0; t1 = u1; break;
+        }
+        o[c] = {u0.x + sg * b0.x, u0.y + sg * b0.y};
+        o[3 + c] = {u1.x + sg * b1.x, u1.y + sg * b1.y};
+        o[6 + c] = {d0.x + sg * t0.x, d0.y + sg * t0.y};
+        o[9 + c] = {d1.x + sg * t1.x, d1.y + sg * t1.y};
+    }
+}
+
+// one thread per (site of parity par, mu)
+__global__ __launch_bounds__(256) void k_force(const cd* __restrict__ xown, const cd* __restrict__ xoth,
+                                               const cd* __restrict__ Uown, Geom g, int par, int Ns, double kappa,
+                                               double* __restrict__ F) {
+    const int tid = blockIdx.x * 256 + threadIdx.x;
+    if (tid >= g.Vh * 4) return;
+    const int cb = tid >> 2, mu = tid & 3;
+    int nb[8];
+    neighbours(g, cb, par, nb);
+    const int cbf = mu == 0 ? nb[0] : mu == 1 ? nb[2] : mu == 2 ? nb[4] : nb[6];
+    cd B1[9], B2[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) B1[q] = B2[q] = {0, 0};
+    for (int s = 0; s < Ns; s++) {
+        const int sb = Ns - 1 - s;
+        cd xf[12], x0[12], y0[12], yf[12], v[12], w[12];
+#pragma unroll
+        for (int j = 0; j < 12; j++) {
+            xf[j] = xoth[((size_t)cbf * 12 + j) * Ns + s];
+            x0[j] = xown[((size_t)cb * 12 + j) * Ns + s];
+            const double g5 = j < 6 ? 1.0 : -1.0;  // y_s = gamma_5 x_{Ns-1-s}
+            const cd a = xown[((size_t)cb * 12 + j) * Ns + sb], b = xoth[((size_t)cbf * 12 + j) * Ns + sb];
+            y0[j] = {g5 * a.x, g5 * a.y};
+            yf[j] = {g5 * b.x, g5 * b.y};
+        }
+        gamma_apply(v, xf, mu, -1.0);
+        gamma_apply(w, x0, mu, +1.0);
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++)
+#pragma unroll
+                for (int sp = 0; sp < 4; sp++) {  // B[i][k] += v[sp][i] conj(y[sp][k])
+                    B1[3 * i + k] = cjmadd(B1[3 * i + k], y0[3 * sp + k], v[3 * sp + i]);
+                    B2[3 * i + k] = cjmadd(B2[3 * i + k], yf[3 * sp + k], w[3 * sp + i]);
+                }
+    }
+    cd U[9], M[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) U[q] = Uown[((size_t)cb * 4 + mu) * 9 + q];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {  // M = U B1 - B2 U^dag
+            cd m = {0, 0};
+#pragma unroll
+            for (int l = 0; l < 3; l++) {
+                m = cmadd(m, U[3 * i + l], B1[3 * l + k]);
+                const cd b = B2[3 * i + l], u = U[3 * k + l];  // (U^dag)[l][k] = conj(U[k][l])
+                m.x -= b.x * u.x + b.y * u.y;
+                m.y -= b.y * u.x - b.x * u.y;
+            }
+            M[3 * i + k] = m;
+        }
+    // Tr[lambda^a M] = sum_ij lambda^a_ij M_ji, then Tr[T^a M] = Tr[lambda^a M] / 2
+    const double r3 = 0.57735026918962576451;  // 1 / sqrt(3)
+    cd tr[8];
+    tr[0] = cadd(M[3], M[1]);
+    tr[1] = {M[3].y - M[1].y, -M[3].x + M[1].x};                // -i M10 + i M01
+    tr[2] = csub(M[0], M[4]);
+    tr[3] = cadd(M[6], M[2]);
+    tr[4] = {M[6].y - M[2].y, -M[6].x + M[2].x};                // -i M20 + i M02
+    tr[5] = cadd(M[7], M[5]);
+    tr[6] = {M[7].y - M[5].y, -M[7].x + M[5].x};                // -i M21 + i M12
+    tr[7] = {r3 * (M[0].x + M[4].x - 2 * M[8].x), r3 * (M[0].y + M[4].y - 2 * M[8].y)};
+    int lex;
+    {
+        int xh = cb % g.Lxh, r = cb / g.Lxh;
+        const int y = r % g.Ly;
+        r /= g.Ly;
+        const int z = r % g.Lz, t = r / g.Lz;
+        const int x = 2 * xh + ((y + z + t + par) & 1);
+        lex = x + g.Lx * (y + g.Ly * (z + g.Lz * t));
+    }
+    double* out = F + ((size_t)mu * (2 * (size_t)g.Vh) + lex) * 8;
+#pragma unroll
+    for (int a = 0; a < 8; a++) out[a] = -(kappa / 2) * (tr[a].y / 2);
+}
+
+hipError_t launch_force(const cd* xown, const cd* xoth, const cd* Uown, const Geom& g, int par, int Ns, double kappa,
+                        double* F, hipStream_t st) {
+    if (Ns < 2 || Ns > MAXNS) return hipErrorInvalidValue;
+    const int grid = (int)(((size_t)g.Vh * 4 + 255) / 256);
+    hipLaunchKernelGGL(k_force, dim3(grid), dim3(256), 0, st, xown, xoth, Uown, g, par, Ns, kappa, F);
+    return hipGetLastError();
+}
+
+}  // namespace eofa

@@ -68,6 +68,8 @@ def load():
         "eofa_hinv": [P, D, D, P, P, C.POINTER(C.c_double), C.POINTER(SolveParams), C.POINTER(SolveInfo)],
         "eofa_chiral_action": [P, I, D, D, D, P, P, C.POINTER(C.c_double), C.POINTER(SolveParams),
                                C.POINTER(SolveInfo)],
+        "eofa_chiral_force": [P, I, D, D, D, P, P, C.POINTER(C.c_double), C.POINTER(SolveParams),
+                              C.POINTER(SolveInfo)],
         "eofa_chiral_action_batch": [P, I, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double), PP, PP, C.POINTER(C.c_double),
                                      C.POINTER(SolveParams), C.POINTER(SolveInfo)],
@@ -104,7 +106,7 @@ def exported_symbols():
     """Names the library exports (for the ABI test)."""
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
-                        "eofa_chiral_action", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
+                        "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
                         "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
                         "eofa_hop_timing", "eofa_graph_stats", "eofa_hop_timing_reset", "eofa_set_precond",
@@ -217,6 +219,20 @@ class Context:
                                          C.byref(S), C.byref(p), C.byref(info))
         self._check(st, "chiral_action")
         return Result(out, S.value, [info.as_dict()])
+
+    def chiral_force(self, chir, m3, m4, mo, phi, p=None):
+        """Fermion force of one chiral action: (F[mu][t][z][y][x][a] float64 on the device, S, info)."""
+        p = p or params()
+        phi = self._c128(phi, self.shape4)
+        Lx, Ly, Lz, Lt = self.dims
+        F = self.torch.empty((4, Lt, Lz, Ly, Lx, 8), dtype=self.torch.float64, device=phi.device)
+        self._prep_ws(p)
+        S = C.c_double()
+        info = SolveInfo()
+        st = self.lib.eofa_chiral_force(self.h, int(chir), float(m3), float(m4), float(mo), _ptr(phi), _ptr(F),
+                                        C.byref(S), C.byref(p), C.byref(info))
+        self._check(st, "chiral_force")
+        return F, S.value, info.as_dict()
 
     def hinv(self, phi, m_lo, m_hi, p=None):
         p = p or params()
