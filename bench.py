@@ -197,8 +197,9 @@ def main():
 
     sched64 = tune["fp64"]["sched"]
     traffic = measured_traffic(args.traffic, dims, Ns, sched64)
-    kern = ("k_hop_tw<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p; t-walk schedule)" if sched64[0] == 3
-            else "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)")
+    kern = {3: "k_hop_tw<16, false, HM_SITE, false, double, false> (u = A_T^{-1} H_eo p; t-walk schedule)",
+            5: "k_hop_tw<16, false, HM_SITE, false, double, true> (u = A_T^{-1} H_eo p; t-walk schedule, x "
+               "neighbours from LDS)"}.get(sched64[0], "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)")
 
     Vh = int(np.prod(dims)) // 2
     alg_bytes = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)

@@ -1354,19 +1354,21 @@ std::vector<Sched> sched_candidates(const eofa_ctx* ctx, int prec) {
                 }
     }
     if (prec != EOFA_MIXED_FP16) {
-        // t-walk: patches of 8 .. 64 segments per XCD, chunks of 16 slabs or the whole t extent, with
-        // and without 48 KB of reserved LDS (one workgroup per CU)
+        // t-walk (mode 3; mode 5 with the x neighbours from LDS): patches of 8 .. 64 segments per XCD,
+        // chunks of 16 slabs or the whole t extent, with and without 48 KB of reserved LDS
         for (int ty : opts)
             for (int tz : opts)
                 for (int tt : {16, g.Lt})
-                    for (int pad : {0, 48}) {
-                        const Sched s{3, 1, ty, tz, tt, nyb, pad};
-                        const int per = ty * tz;
-                        if (per < 8 || per > 64 || tw_grid(g, ctx->Ns, s) == 0) continue;
-                        bool dup = false;
-                        for (const Sched& o : c) dup |= (o.mode == 3 && o.ty == ty && o.tz == tz && o.tt == tt && o.ord == pad);
-                        if (!dup) c.push_back(s);
-                    }
+                    for (int pad : {0, 48})
+                        for (int mode : {3, 5}) {
+                            const Sched s{mode, 1, ty, tz, tt, nyb, pad};
+                            const int per = ty * tz;
+                            if (per < 8 || per > 64 || tw_grid(g, ctx->Ns, s) == 0) continue;
+                            bool dup = false;
+                            for (const Sched& o : c)
+                                dup |= (o.mode == mode && o.ty == ty && o.tz == tz && o.tt == tt && o.ord == pad);
+                            if (!dup) c.push_back(s);
+                        }
     }
     return c;
 }

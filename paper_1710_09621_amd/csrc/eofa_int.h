@@ -17,7 +17,8 @@ enum : int { HM_LIN = 0, HM_SITE = 1, HM_SCHUR_W = 2, HM_SCHUR_Q = 3, HM_DT = 4,
 // mode 3 (single-system FP64 / FP32 hop only): t-walk.  A workgroup owns one segment of 256 / Ns
 // sites of a t-slab and walks tt consecutive slabs; the segments form an nyb x (segments / nyb) grid
 // and the workgroups that run together on an XCD take a ty x tz patch of it; ord = KB of LDS reserved
-// per workgroup (caps the workgroups per CU).  The other kernels read mode 3 as mode 0.
+// per workgroup (caps the workgroups per CU).  mode 5: mode 3 with the x-direction columns read from LDS,
+// for segments that hold whole x-lines.  The other kernels read modes 3 and 5 as mode 0.
 struct Sched {
     int mode, xcd, ty, tz, tt, nyb, ord;
 };

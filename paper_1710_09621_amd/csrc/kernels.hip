@@ -396,9 +396,12 @@ __device__ __forceinline__ void tw_carry(cpx<R>* cw, const cpx<R>* __restrict__ 
     for (int j = 0; j < 6; j++) cw[j * 256] = w[j];
 }
 
-template <int NS, bool DAG, int MODE, bool RED, typename R>
+// XL: the segment holds whole x-lines, and the input columns of the current slab (loaded one step earlier
+// as the slab-(t+1) columns) are kept in LDS (xl[12][256]), so the x-direction terms read LDS.
+template <int NS, bool DAG, int MODE, bool RED, typename R, bool XL>
 __device__ __forceinline__ void tw_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9], const SiteOpL<NS>& sA,
-                                        const SiteOpL<NS>& sB, int cb, int s, int lane, cpx<R>* cw, double& nrm) {
+                                        const SiteOpL<NS>& sB, int cb, int s, int lane, cpx<R>* cw, double& nrm,
+                                        cpx<R> (*xl)[256]) {
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
     const int ls = threadIdx.x / NS;
@@ -411,7 +414,26 @@ __device__ __forceinline__ void tw_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9],
     cpx<R> z[12];
 #pragma unroll
     for (int j = 0; j < 12; j++) z[j] = {0, 0};
-    hop_mu<NS, DAG, 0>(z, a.in, sU[ls][0], sU[ls][4], nb, s);
+    if constexpr (XL) {  // x +- 1 are sites of this segment: lanes (ls + nb - cb) * NS + s
+        const int lf = (ls + nb[0] - cb) * NS + s, lb = (ls + nb[1] - cb) * NS + s;
+        cpx<R> p[12], h[6], w[6], U[9];
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j] = xl[j][lf];
+        project<0, SF>(p, h);
+#pragma unroll
+        for (int k = 0; k < 9; k++) U[k] = sU[ls][0][k];
+        link_mul<false>(U, h, w);
+        reconstruct<0, SF>(z, w);
+#pragma unroll
+        for (int j = 0; j < 12; j++) p[j] = xl[j][lb];
+        project<0, SB>(p, h);
+#pragma unroll
+        for (int k = 0; k < 9; k++) U[k] = sU[ls][4][k];
+        link_mul<true>(U, h, w);
+        reconstruct<0, SB>(z, w);
+    } else {
+        hop_mu<NS, DAG, 0>(z, a.in, sU[ls][0], sU[ls][4], nb, s);
+    }
     HOP_FENCE();
     hop_mu<NS, DAG, 1>(z, a.in, sU[ls][1], sU[ls][5], nb, s);
     HOP_FENCE();
@@ -422,6 +444,11 @@ __device__ __forceinline__ void tw_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9],
         // the next step's link loads would make their wait (an in-order count) wait for it as well
         cpx<R> p[12], h[6], w[6], U[9];
         load_col<NS, false>(p, a.in, (size_t)nb[6], s, 0);
+        if constexpr (XL) {  // every lane has read this slab's columns: keep the next slab's
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 12; j++) xl[j][threadIdx.x] = p[j];
+        }
         project<3, SF>(p, h);
 #pragma unroll
         for (int k = 0; k < 9; k++) U[k] = sU[ls][3][k];
@@ -445,10 +472,11 @@ __device__ __forceinline__ void tw_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9],
 #ifndef HOP_TW_WAVES
 #define HOP_TW_WAVES 1
 #endif
-template <int NS, bool DAG, int MODE, bool RED, typename R>
+template <int NS, bool DAG, int MODE, bool RED, typename R, bool XL>
 __global__ __launch_bounds__(256, HOP_TW_WAVES) void k_hop_tw(const HopArgs<R> a) {
     if (a.done && *a.done != 0.0) return;
     __shared__ cpx<R> sU[256 / NS][8][9];
+    __shared__ cpx<R> xl[XL ? 12 : 1][256];  // XL: the current slab's input columns of this segment
     __shared__ SiteOpL<NS> sA, sB;
     {
         OpsShare<NS> sh;
@@ -466,9 +494,16 @@ __global__ __launch_bounds__(256, HOP_TW_WAVES) void k_hop_tw(const HopArgs<R> a
     __shared__ cpx<R> carry[2][6][256];
     tw_carry<NS, DAG>(&carry[0][0][threadIdx.x], a.in, a.Uoth, i + st * (t0 == 0 ? a.g.Lt - 1 : t0 - 1), s);
     tw_carry<NS, DAG>(&carry[1][0][threadIdx.x], a.in, a.Uoth, i + st * t0, s);
+    if constexpr (XL) {  // slab t0's columns; published by the first step's barriers
+        cpx<R> p[12];
+        load_col<NS, false>(p, a.in, (size_t)(i + st * t0), s, 0);
+#pragma unroll
+        for (int j = 0; j < 12; j++) xl[j][threadIdx.x] = p[j];
+    }
     double nrm = 0.0;
     for (int k = 0; k < TC; k++)
-        tw_step<NS, DAG, MODE, RED>(a, sU, sA, sB, i + st * (t0 + k), s, lane, &carry[k & 1][0][threadIdx.x], nrm);
+        tw_step<NS, DAG, MODE, RED, R, XL>(a, sU, sA, sB, i + st * (t0 + k), s, lane, &carry[k & 1][0][threadIdx.x],
+                                           nrm, xl);
     if constexpr (RED) {
         __shared__ double lds[4];
         finish_sum(a.red, block_sum256(nrm, lds));
@@ -968,9 +1003,10 @@ hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, 
     default: return hipErrorInvalidValue;                              \
     }
 
-// Whether schedule sc (mode 3) fits the lattice and Ns; the t-walk grid size when it does, else 0.
+// Whether schedule sc (mode 3 or 5) fits the lattice and Ns; the t-walk grid size when it does, else 0.
 int tw_grid(const Geom& g, int Ns, const Sched& sc) {
-    if (sc.mode != 3 || Ns < 8) return 0;
+    if ((sc.mode != 3 && sc.mode != 5) || Ns < 8) return 0;
+    if (sc.mode == 5 && (256 / Ns) % g.Lxh) return 0;  // the segment must hold whole x-lines
     const long slab = (long)g.Vh / g.Lt;
     if ((slab * Ns) % 256 != 0) return 0;
     const long nseg = slab * Ns / 256;
@@ -990,17 +1026,23 @@ template <typename K> static size_t lds_room(K kern) {
 template <typename R>
 hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st) {
     const size_t nthreads = (size_t)a.g.Vh * Ns;
-    const bool tw = a.sc.mode == 3;
+    const bool tw = a.sc.mode == 3 || a.sc.mode == 5;
     const int grid = tw ? tw_grid(a.g, Ns, a.sc) : (int)((nthreads + 255) / 256);
     if (grid <= 0) return hipErrorInvalidValue;
     const size_t pad = tw ? (size_t)a.sc.ord * 1024 : 0;  // LDS reserved to cap workgroups per CU
 #define HOP_L(D, M, RD)                                                                                  \
     do {                                                                                                 \
         if constexpr (NS >= 8) {                                                                         \
+            if (tw && a.sc.mode == 5) {                                                                  \
+                static const size_t room = lds_room(k_hop_tw<NS, D, M, RD, R, true>);                    \
+                hipLaunchKernelGGL((k_hop_tw<NS, D, M, RD, R, true>), dim3(grid), dim3(256),              \
+                                   pad < room ? pad : room, st, a);                                      \
+                break;                                                                                   \
+            }                                                                                            \
             if (tw) {                                                                                    \
-                static const size_t room = lds_room(k_hop_tw<NS, D, M, RD, R>);                          \
-                hipLaunchKernelGGL((k_hop_tw<NS, D, M, RD, R>), dim3(grid), dim3(256), pad < room ? pad : room, \
-                                   st, a);                                                               \
+                static const size_t room = lds_room(k_hop_tw<NS, D, M, RD, R, false>);                   \
+                hipLaunchKernelGGL((k_hop_tw<NS, D, M, RD, R, false>), dim3(grid), dim3(256),             \
+                                   pad < room ? pad : room, st, a);                                      \
                 break;                                                                                   \
             }                                                                                            \
         }                                                                                                \

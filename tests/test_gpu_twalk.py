@@ -1,4 +1,4 @@
-"""The t-walk hop schedule (workgroups walking t with the backward t term carried, mode 3) against the
+"""The t-walk hop schedules (workgroups walking t with the backward t term carried, modes 3 and 5) against the
 default schedule and the oracle: every operator bit-for-bit equal to the default schedule's in FP64 and
 FP32 for every t-walk schedule the autotuner may pick, the FP64 D_T against the oracle, and a CG solve
 under a t-walk schedule checked by the oracle's residual."""
@@ -17,7 +17,7 @@ OPS = ["DW", "HOP", "DT", "DT_DAG", "HT", "AT_INV", "SCHUR", "SCHUR_DAG", "SCHUR
 
 
 def tw_schedules(dims, Ns):
-    """The mode-3 candidates of the autotuner: [3, xcd, ty, tz, tt, nyb, KB of reserved LDS]."""
+    """The t-walk candidates of the autotuner: [3 or 5, xcd, ty, tz, tt, nyb, KB of reserved LDS]."""
     Lxh, Ly, Lz, Lt = dims[0] // 2, dims[1], dims[2], dims[3]
     if (Lxh * Ly * Ns) % 256:
         return []
@@ -31,7 +31,10 @@ def tw_schedules(dims, Ns):
                 if Lt % tt:
                     continue
                 for pad in (0, 48):
-                    out.append([3, 1, ty, tz, tt, nyb, pad])
+                    for mode in (3, 5):  # 5: x neighbours from LDS, segments of whole x-lines
+                        if mode == 5 and (256 // Ns) % Lxh:
+                            continue
+                        out.append([mode, 1, ty, tz, tt, nyb, pad])
     return out
 
 
