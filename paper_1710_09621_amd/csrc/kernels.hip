@@ -525,7 +525,30 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
     neighbours(a.g, cb, a.par, nb);
     __shared__ cpx<R> sU[256 / NS][8][9];
     __shared__ double lds[4];
-    stage_links<NS>(sU, a.Uown, a.Uoth, cb, nb, s);
+    // LDS copies of every system's site-local operators (dynamic LDS: nr for HM_SITE, 2 nr for HM_SCHUR_W),
+    // loaded with the links in one round trip
+    extern __shared__ double hop_mr_dyn[];
+    SiteOpL<NS>* sOps = (SiteOpL<NS>*)hop_mr_dyn;
+    constexpr int NOP = MODE == HM_SITE ? 1 : MODE == HM_SCHUR_W ? 2 : 0;
+    if constexpr (NOP > 0) {
+        SiteOpShare<NS> sh[NRMAX * NOP];
+#pragma unroll
+        for (int r = 0; r < NRMAX; r++)
+            if (r < a.nr) {
+                siteop_fetch<NS>(sh[NOP * r], *a.opA[r]);
+                if constexpr (NOP == 2) siteop_fetch<NS>(sh[NOP * r + 1], *a.opB[r]);
+            }
+        stage_links<NS>(sU, a.Uown, a.Uoth, cb, nb, s, [&] {
+#pragma unroll
+            for (int r = 0; r < NRMAX; r++)
+                if (r < a.nr) {
+                    siteop_store<NS>(sOps[NOP * r], sh[NOP * r]);
+                    if constexpr (NOP == 2) siteop_store<NS>(sOps[NOP * r + 1], sh[NOP * r + 1]);
+                }
+        });
+    } else {
+        stage_links<NS>(sU, a.Uown, a.Uoth, cb, nb, s);
+    }
     const size_t base = (size_t)cb * 12 * NS + s;
     for (int r = 0; r < a.nr; r++) {
         const double* S = a.scal + r * SC_N;
@@ -536,9 +559,9 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
         if constexpr (MODE == HM_SITE) {
 #pragma unroll
             for (int j = 0; j < 12; j++) v[j] = cscale(a.cz, z[j]);
-            site_op<NS, DAG>(v, *a.opA[r], s, lane);
+            site_op<NS, DAG>(v, sOps[r], s, lane);
         } else if constexpr (MODE == HM_SCHUR_W) {
-            site_op<NS, false>(z, *a.opA[r], s, lane);
+            site_op<NS, false>(z, sOps[2 * r], s, lane);
             cpx<R> t[12];
             load_col<NS, H>(t, a.aux[r], (size_t)cb, s, a.g.Vh);
 #pragma unroll
@@ -565,7 +588,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
             for (int j = 0; j < 12; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
             if (!valid) nrm = 0.0;
             if constexpr (MODE == HM_SCHUR_W) {
-                site_op<NS, true>(v, *a.opB[r], s, lane);
+                site_op<NS, true>(v, sOps[2 * r + 1], s, lane);
                 if (valid) store_col<NS, H>(a.out2[r], (size_t)cb, s, a.g.Vh, v);
             }
             const double bs = block_sum256(nrm, lds);
@@ -1075,10 +1098,11 @@ hipError_t launch_hop_mr(int Ns, bool dag, int mode, const HopArgsMR<R>& a, hipS
     if (grid > a.pstride) return hipErrorInvalidValue;
 #define MR_L(D, M)                                                                                       \
     do {                                                                                                 \
+        const size_t ops = (size_t)a.nr * (M == HM_SITE ? 1 : M == HM_SCHUR_W ? 2 : 0) * sizeof(SiteOpL<NS>); \
         if constexpr (sizeof(R) == 4) {                                                                  \
-            if (half) { hipLaunchKernelGGL((k_hop_mr<NS, D, M, R, true>), dim3(grid), dim3(256), 0, st, a); break; } \
+            if (half) { hipLaunchKernelGGL((k_hop_mr<NS, D, M, R, true>), dim3(grid), dim3(256), ops, st, a); break; } \
         }                                                                                                \
-        hipLaunchKernelGGL((k_hop_mr<NS, D, M, R, false>), dim3(grid), dim3(256), 0, st, a);            \
+        hipLaunchKernelGGL((k_hop_mr<NS, D, M, R, false>), dim3(grid), dim3(256), ops, st, a);          \
     } while (0)
 #define MR_MODES(D)                                            \
     switch (mode) {                                            \
