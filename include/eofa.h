@@ -185,10 +185,13 @@ eofa_status eofa_dslash_bench(eofa_ctx *ctx, int prec, int nrep, double *ms, dou
 
 /*
  * Autotuner of the hop kernels' workgroup schedule (XCD-contiguous ranges, 3D tiling of the
- * workgroup grid) for this lattice and storage precision (FP64, FP32 or FP16; each has its own
- * schedule, FP16 for the batch kernels): times every candidate with
- * nrep launches of the fused hop (0: 4) and keeps the fastest for all later solves.
- * sched_out[7] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb, ord} for a persistent cache;
+ * workgroup grid, and for the single-system FP64 / FP32 hop the t-walk forms, in which a workgroup
+ * walks the t direction) for this lattice and storage precision (FP64, FP32 or FP16; each has its
+ * own schedule, FP16 for the batch kernels): times every candidate with
+ * nrep launches of the fused hop (0: 4) and keeps the fastest for all later solves.  Every
+ * schedule gives bitwise the same operator; the CG reductions may sum in another order.
+ * sched_out[7] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb, ord} for a persistent cache
+ * (mode 0: linear, 1: 3D tiles, 3: t-walk, 5: t-walk with the x neighbours from LDS);
  * *best_ms / *base_ms (may be NULL) the chosen and the linear-order launch times.
  */
 eofa_status eofa_autotune(eofa_ctx *ctx, int prec, int nrep, int sched_out[7], double *best_ms,
