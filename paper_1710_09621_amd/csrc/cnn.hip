@@ -290,9 +290,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad3(const unsigned short* __res
     const int r_begin = chunk * chunk_rows + w * quarter;
     const int r_end = min(rows, r_begin + quarter);
     const int sy = g.Lxh, sz = g.Lxh * g.Ly, st = sz * g.Lz;
-    for (int rb = r_begin; rb < r_end; rb += 32) {
+    // operands of the 32 rows at rb (zeros past r_end); the next step's are requested before this step's
+    // 12 MFMAs, so a global round trip overlaps the matrix-core work
+    auto load_ops = [&](int rb, bf16x8& a0, bf16x8& a1, bf16x8 (*b)[2]) {
         const int r8 = rb + kb * 8;  // 8 rows (one site, 8 consecutive s) of this lane's k block
-        bf16x8 a0, a1, b[3][2];
         if (r8 + 8 <= r_end) {
             a0 = *(const bf16x8*)(dYT + (size_t)li * rows + r8);
             a1 = *(const bf16x8*)(dYT + (size_t)(16 + li) * rows + r8);
@@ -314,12 +315,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad3(const unsigned short* __res
                 for (int d = 0; d < 3; d++) { b[d][0][j] = (__bf16)0.0f; b[d][1][j] = (__bf16)0.0f; }
             }
         }
+    };
+    bf16x8 a0, a1, b[3][2];
+    load_ops(r_begin, a0, a1, b);
+    for (int rb = r_begin; rb < r_end; rb += 32) {
+        bf16x8 a0n, a1n, bn[3][2];
+        load_ops(rb + 32, a0n, a1n, bn);
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             acc[d][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[d][0], acc[d][0][0], 0, 0, 0);
             acc[d][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[d][1], acc[d][0][1], 0, 0, 0);
             acc[d][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[d][0], acc[d][1][0], 0, 0, 0);
             acc[d][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[d][1], acc[d][1][1], 0, 0, 0);
+        }
+        a0 = a0n;
+        a1 = a1n;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            b[d][0] = bn[d][0];
+            b[d][1] = bn[d][1];
         }
     }
     // waves 1..3 park their sums in LDS, wave 0 adds them in order and writes the partial
