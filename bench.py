@@ -1,14 +1,20 @@
 """Benchmark of the EOFA solve hot path on one MI355X.
 
-One step = the new mass-preconditioned EOFA sequence of Eq.(new_MP) on the 32^3 x 64, Ns = 16
-lattice (links exp(i 0.7 theta_a t^a), seeded): for (m, m_h, M) = (0.01, 0.1, 1.0) the three
-chiral actions (m,m)/(m,m_h) [-], (m,m_h)/(M,m_h) [+], (M,m_h)/(M,M) [-] applied to --nsrc
-Gaussian sources, every 5D solve to a true residual of 1e-10 in FP64.  Inputs are generated
-on the host and moved to HBM before the timed region.
+Workload: the 32^3 x 64, Ns = 16 lattice (links exp(i 0.7 theta_a t^a), seeded), m0 = 1.3, the R5-symmetric
+optimal weights for [0.05, 6.2], and the new mass-preconditioned sequence of Eq.(new_MP) with
+(m, m_h, M) = (0.01, 0.1, 1.0): chiral actions (m,m)/(m,m_h) [-], (m,m_h)/(M,m_h) [+], (M,m_h)/(M,M) [-].
 
-Prints one JSON line: value = FP64 dslash (fused even-odd hop) throughput in algorithmic GB/s,
-measured with HIP events around every hop launch of the timed steps; roofline, CPU oracle
-baseline and the time to solution of the step ride along.
+One step = the source build and even-odd preparation of the middle action (its 5D system H_T(m, m_h) needs the
+most CG iterations of the three) followed by --niter FP64 CG iterations on its Schur normal equations, with no
+host synchronisation inside the step.  Every kernel of every iteration is timed with HIP events on the
+library's stream.  value = algorithmic GB/s of the FP64 dslash (K1, the fused even-odd hop with its A_T^{-1}
+epilogue) over the timed steps.
+
+Once per invocation, outside the timed steps, the whole sequence is solved to a true residual of 1e-10 on one
+Gaussian source in plain FP64 CG and in the tuned solver (the three systems in one multi-RHS launch sequence,
+FP16-column Krylov storage with FP32 arithmetic and FP64 reliable updates, autotuned schedules, hipGraph blocks
+of 16 iterations); their times and iteration counts go into "tts".  Inputs are generated on the host and moved
+to HBM before anything is timed.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -22,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-HOP_FLOP_PER_SITE = 1320 + 250
+HOP_FLOP_PER_SITE = 1320 + 250  # Wilson hop per site and slice + the A_T^{-1} epilogue
 
 
 def log(*a):
@@ -32,7 +38,6 @@ def log(*a):
 def cpu_baseline(U, dims, Ns, omega, budget_s=12.0):
     """The FP64 oracle's Wilson hop on s-slices of the same lattice, timed on the host cores.
     Bytes per output 5D site are counted exactly as for the GPU hop (in + out + links/Ns)."""
-    import numpy as np
     from oracle import oracle as O
     from paper_1710_09621_amd import inputs as IN
     O.build()
@@ -84,10 +89,11 @@ def measured_traffic(path, dims, Ns, sched):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nsrc", type=int, default=1, help="Gaussian sources per step")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--niter", type=int, default=16, help="FP64 CG iterations per step")
     ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--no-tts", action="store_true", help="skip the once-per-run time-to-solution comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-iter", type=int, default=50000)
     ap.add_argument("--tune-cache", type=str, default=None)
@@ -97,7 +103,8 @@ def main():
                     help="JSON with measured HBM bytes per hop launch (from rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the solve path has no multi-GPU form); "
+                                   "run it with --gpus 1"}))
         sys.exit(2)
 
     import numpy as np
@@ -111,89 +118,92 @@ def main():
     t0 = time.time()
     U = IN.gauge_links(dims, eps, seed)
     omega = IN.optimal_omega(Ns)
-    phis = [IN.gaussian_spinor(dims[::-1], seed * 1000 + j) for j in range(args.nsrc)]
+    phi = IN.gaussian_spinor(dims[::-1], seed * 1000)
     log(f"inputs ready in {time.time() - t0:.1f}s: dims={dims} Ns={Ns}")
 
     dev = torch.device("cuda:0")
     ctx = E.Context(dims, Ns, IN.M0, omega, device="cuda:0")
     ctx.set_gauge(torch.from_numpy(U).to(dev))
-    phis_d = [torch.from_numpy(p).to(dev) for p in phis]
+    phi_d = torch.from_numpy(phi).to(dev)
     if len(masses) == 3:   # new MP, Eq.(new_MP)
         m, mh, M = masses
         actions = [(-1, m, m, mh), (+1, m, mh, M), (-1, M, mh, M)]
-        wl = f"EOFA new-MP solve sequence (m, m_h, M) = ({m}, {mh}, {M}), 3 chiral actions"
+        wl = f"EOFA new-MP sequence (m, m_h, M) = ({m}, {mh}, {M})"
     else:                  # no MP, Eq.(noMP)
         m, M = masses
         actions = [(-1, m, m, M), (+1, m, M, M)]
-        wl = f"EOFA (m, m)/(M, M) = ({m}, {M}) without MP, 2 chiral actions"
-    P64 = E.params(tol=1e-10, max_iter=args.max_iter)
+        wl = f"EOFA (m, m)/(M, M) = ({m}, {M}) without MP"
+    # the step's system: the action whose H_T needs the most iterations (the middle one of the new MP)
+    step_action = actions[1]
     tuned_prec = {"fp16": E.MIXED_FP16, "fp32": E.MIXED_FP32}[args.tuned_prec]
-    PT = E.params(tol=1e-10, max_iter=args.max_iter, prec=tuned_prec)
 
     # hop-kernel schedules for this lattice (in-house autotuner), outside the timed region
     tune = {}
     for prec, nm in ((E.FP64, "fp64"), (tuned_prec, args.tuned_prec)):
+        ta = time.time()
         tune[nm] = ctx.autotune(prec=prec, cache=args.tune_cache)
-        log(f"autotune {nm}: {tune[nm]}")
-
-    def run(P, tag):
-        res = []
-        for phi in phis_d:
-            for a in actions:
-                ta = time.perf_counter()
-                r = ctx.chiral_action(*a, phi, P)
-                log(f"  [{tag}] action {a}: {time.perf_counter() - ta:.2f}s iters={r.info[0]['iters']} "
-                    f"resid={r.info[0]['true_rel_resid']:.2e} S={r.S:.10e}")
-                res.append(r)
-        return res
+        log(f"autotune {nm}: {tune[nm]} ({time.time() - ta:.1f}s)")
 
     def step():
-        """One pass of the hot path: the sequence in plain FP64 CG, then in the tuned solver."""
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.hop_timing(True)
-        plain = run(P64, "fp64")
-        torch.cuda.synchronize()
-        ctx.hop_timing(False)
-        t1 = time.perf_counter()
-        acts = [a for _ in phis_d for a in actions]
-        srcs = [phi for phi in phis_d for _ in actions]
-        tuned = ctx.chiral_action_batch(acts, srcs, PT)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for a, r in zip(acts, tuned):
-            log(f"  [tuned] action {a}: iters={r.info[0]['iters']} updates={r.info[0]['reliable_updates']} "
-                f"resid={r.info[0]['true_rel_resid']:.2e} S={r.S:.10e}")
-        return plain, tuned, t1 - t0, t2 - t1
+        return ctx.cg_block(step_action[0], step_action[1], step_action[2], phi_d, args.niter)
 
     for w in range(args.warmup):
-        t1 = time.time()
+        ta = time.time()
         step()
-        log(f"warmup step {w} {time.time() - t1:.2f}s")
-    torch.cuda.synchronize()
-    ctx.hop_timing_reset()
+        log(f"warmup step {w}: {time.time() - ta:.3f}s")
+    ctx.kernel_timing(enable=True, reset=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    plain, tuned, tp, tt = [], [], 0.0, 0.0
+    rel = None
     for k in range(args.steps):
-        a, b, x, y = step()
-        plain += a
-        tuned += b
-        tp += x
-        tt += y
-        log(f"step {k} done")
+        rel = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
-    ht = ctx.hop_timing(False)
-    hop_gbs = ht["bytes"] / (ht["ms"] * 1e-3) / 1e9 if ht["ms"] > 0 else None
-    per_launch_ms = ht["ms"] / max(ht["launches"], 1)
-    iters = [r.info[0]["iters"] for r in plain]
-    iters_t = [r.info[0]["iters"] for r in tuned]
-    resid = [r.info[0]["true_rel_resid"] for r in plain + tuned]
-    dS = max(abs(a.S - b.S) / abs(a.S) for a, b in zip(plain, tuned))
-    log(f"timed {args.steps} steps in {el:.2f}s (plain {tp:.2f}s, tuned {tt:.2f}s); hop {ht['launches']} launches "
-        f"avg {per_launch_ms:.4f} ms -> {hop_gbs:.1f} GB/s; iters {iters} / {iters_t}; max resid {max(resid):.2e}; "
-        f"max |dS|/S {dS:.1e}")
+    kt = ctx.kernel_timing(enable=False)
+    log(f"timed {args.steps} steps of {args.niter} CG iterations in {el:.3f}s; |r|/|r0| after a step {rel:.3e}")
+    for nm, v in kt.items():
+        log(f"  {nm:8s} {v['launches']:5d} launches, {v['ms'] / max(v['launches'], 1):.4f} ms each, "
+            f"{v['bytes'] / max(v['ms'], 1e-12) / 1e6:.1f} GB/s")
+    k1 = kt["hop"]
+    hop_gbs = k1["bytes"] / (k1["ms"] * 1e-3) / 1e9
+    per_launch_ms = k1["ms"] / k1["launches"]
+    it_ms = sum(v["ms"] for v in kt.values()) / k1["launches"]
+    it_bytes = sum(v["bytes"] for v in kt.values()) / k1["launches"]
+    Vh = int(np.prod(dims)) // 2
+    alg_bytes = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)
+
+    tts = None
+    if not args.no_tts:
+        P64 = E.params(tol=1e-10, max_iter=args.max_iter)
+        PT = E.params(tol=1e-10, max_iter=args.max_iter, prec=tuned_prec, use_graph=1)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        plain = []
+        for a in actions:
+            r = ctx.chiral_action(*a, phi_d, P64)
+            log(f"  [fp64] action {a}: iters={r.info[0]['iters']} resid={r.info[0]['true_rel_resid']:.2e} "
+                f"S={r.S:.10e} ({r.info[0]['seconds']:.2f}s)")
+            plain.append(r)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        g0 = ctx.graph_stats()
+        tuned = ctx.chiral_action_batch(actions, [phi_d] * len(actions), PT)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        g1 = ctx.graph_stats()
+        for a, r in zip(actions, tuned):
+            log(f"  [tuned] action {a}: iters={r.info[0]['iters']} updates={r.info[0]['reliable_updates']} "
+                f"resid={r.info[0]['true_rel_resid']:.2e} S={r.S:.10e}")
+        resid = [r.info[0]["true_rel_resid"] for r in plain + tuned]
+        dS = max(abs(a.S - b.S) / abs(a.S) for a, b in zip(plain, tuned))
+        tts = {"plain_fp64_s": round(tb - ta, 3), "plain_iters": [r.info[0]["iters"] for r in plain],
+               "tuned_s": round(tc - tb, 3), "tuned_iters": [r.info[0]["iters"] for r in tuned],
+               "tuned": f"multi-RHS batch (the {len(actions)} systems in one launch sequence), "
+                        f"{args.tuned_prec.upper()}-storage reliable-update CG, autotuned hop schedule, hipGraph "
+                        f"blocks of 16 iterations ({g1['replays'] - g0['replays']} replays)",
+               "speedup": round((tb - ta) / (tc - tb), 3), "max_true_rel_resid": max(resid), "max_rel_dS": dS,
+               "sources": 1}
+        log(f"time to solution: plain {tb - ta:.2f}s, tuned {tc - tb:.2f}s ({tts['speedup']:.2f}x)")
 
     sched64 = tune["fp64"]["sched"]
     traffic = measured_traffic(args.traffic, dims, Ns, sched64)
@@ -201,8 +211,6 @@ def main():
             5: "k_hop_tw<16, false, HM_SITE, false, double, true> (u = A_T^{-1} H_eo p; t-walk schedule, x "
                "neighbours from LDS)"}.get(sched64[0], "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)")
 
-    Vh = int(np.prod(dims)) // 2
-    alg_bytes = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle baseline")
@@ -210,7 +218,7 @@ def main():
 
     out = {
         "metric": "DWF dslash HBM GB/s; EOFA CG time-to-1e-10 residual, tuned vs plain FP64",
-        "value": round(hop_gbs, 2) if hop_gbs else None,
+        "value": round(hop_gbs, 2),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -221,25 +229,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl} x {args.nsrc} Gaussian source(s), every 5D solve to a true residual of 1e-10, "
-                               f"once in plain FP64 CG and once in the tuned solver",
+        "config": {"workload": f"{wl}; one step = source build + even-odd preparation of the action "
+                               f"{step_action} (5D system H_T({step_action[1]}, {step_action[2]})) + {args.niter} "
+                               f"FP64 CG iterations on its Schur normal equations",
                    "lattice": "x".join(map(str, dims)), "Ns": Ns, "eps": eps, "seed": seed, "m0": IN.M0,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(hop_gbs, 2) if hop_gbs else None, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(hop_gbs / HBM_PEAK_GBS, 4) if hop_gbs else None,
-                     "traffic": traffic,
-                     "kernel": kern,
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(per_launch_ms, 5),
-                     # 1320 flop per site and slice for the Wilson hop + 250 for the A_T^{-1} epilogue
+                   "cg_iterations_per_step": args.niter, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(hop_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(hop_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kern, "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(per_launch_ms, 5),
+                     "launches": k1["launches"],
                      "flop_per_launch": HOP_FLOP_PER_SITE * Vh * Ns,
-                     "fp64_tflops": round(HOP_FLOP_PER_SITE * Vh * Ns / (per_launch_ms * 1e-3) / 1e12, 3)
-                     if hop_gbs else None},
-        "tts": {"plain_fp64_s_per_step": round(tp / args.steps, 3), "plain_iters": iters,
-                "tuned_s_per_step": round(tt / args.steps, 3), "tuned_iters": iters_t,
-                "tuned": f"multi-RHS batch (all systems of the step in one launch sequence), {args.tuned_prec.upper()}-storage "
-                         "reliable-update CG, autotuned hop schedule",
-                "speedup": round(tp / tt, 3), "max_true_rel_resid": max(resid), "max_rel_dS": dS,
-                "schedules": {k: v["sched"] for k, v in tune.items()}},
+                     "fp64_tflops": round(HOP_FLOP_PER_SITE * Vh * Ns / (per_launch_ms * 1e-3) / 1e12, 3)},
+        "cg_iteration": {"ms": round(it_ms, 4), "alg_bytes": it_bytes, "gbs": round(it_bytes / it_ms / 1e6, 2),
+                         "frac": round(it_bytes / it_ms / 1e6 / HBM_PEAK_GBS, 4),
+                         "kernels": {nm: {"ms": round(v["ms"] / max(v["launches"], 1), 4),
+                                          "gbs": round(v["bytes"] / max(v["ms"], 1e-12) / 1e6, 1)}
+                                     for nm, v in kt.items()}},
+        "tts": tts,
+        "schedules": {k: v["sched"] for k, v in tune.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

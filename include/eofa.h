@@ -162,16 +162,44 @@ eofa_status eofa_hinv_batch(eofa_ctx *ctx, int n, const double *m_lo, const doub
 eofa_status eofa_solve_ht(eofa_ctx *ctx, double m_plus, double m_minus, const void *b5, void *x5,
                           const eofa_solve_params *params, eofa_solve_info *info);
 
+/* n systems H_T(m_plus[j], m_minus[j]) x5[j] = b5[j] solved together (the multi-RHS form of eofa_solve_ht; host
+ * arrays of n device pointers to 5D canonical buffers, b5[j] != x5[j]).  Up to 8 systems share each launch
+ * sequence, as in eofa_chiral_action_batch; info[j] per system (may be NULL). */
+eofa_status eofa_solve_ht_batch(eofa_ctx *ctx, int n, const double *m_plus, const double *m_minus,
+                                const void *const *b5, void *const *x5, const eofa_solve_params *params,
+                                eofa_solve_info *info);
+
 /* out = op(in) (5D canonical device buffers, may not alias) in the given storage precision
  * (EOFA_FP64 or EOFA_MIXED_FP32: FP32 storage and arithmetic, result widened to complex128). */
 eofa_status eofa_apply(eofa_ctx *ctx, int op, double m_plus, double m_minus, const void *in, void *out,
                        eofa_precision prec);
 
-/* Device time (ms, HIP events) and launch count of the FP64 even-odd hop kernel since the
- * last reset, for throughput accounting.  enable != 0 starts recording events around every
- * hop launch (adds a small overhead); eofa_hop_timing_reset clears the counters. */
-eofa_status eofa_hop_timing(eofa_ctx *ctx, int enable, double *ms, long *launches, double *bytes);
-eofa_status eofa_hop_timing_reset(eofa_ctx *ctx);
+/*
+ * Kernel classes of one FP64 CG iteration on the even-odd normal equations (the solves that Sec. I names as
+ * the cost of HMC): K1 u = A_T^{-1} H_eo p (the hop with its site-local epilogue); K2 w = Dhat p,
+ * wt = A_T^{-dag} w and |w|^2; K3 at = A_T^{-dag} gamma_5 H_eo gamma_5 wt; K4 r -= alpha (w - H_oe at / 4)
+ * and |r|^2; K5 x += alpha p, p = r + beta p.
+ */
+enum { EOFA_K_HOP = 0, EOFA_K_SCHUR_W = 1, EOFA_K_HOP_DAG = 2, EOFA_K_SCHUR_Q = 3, EOFA_K_XP = 4, EOFA_NKERN = 5 };
+typedef struct {
+    double ms[EOFA_NKERN];     /* summed device time, HIP events recorded on the context's stream around each launch */
+    long launches[EOFA_NKERN];
+    double bytes[EOFA_NKERN];  /* summed algorithmic HBM bytes: every spinor field a launch reads or writes once
+                                  (12 Ns complex128 per 4D site of the output parity), its 8 links once */
+} eofa_kernel_stats;
+/* Per-kernel timing of the FP64 CG iterations of every later solve and eofa_cg_block: reset != 0 clears the
+ * counters, enable != 0 records events from now on (a few microseconds per launch), 0 stops.  *stats (may be
+ * NULL) receives the counters after the stream has drained.  Graph replays are not timed. */
+eofa_status eofa_kernel_timing(eofa_ctx *ctx, int enable, int reset, eofa_kernel_stats *stats);
+
+/*
+ * Benchmark step of the FP64 solve path: the source build (R5 gamma_5 of Om (x) P_chir phi) and even-odd
+ * preparation of one chiral action (chir, m3, m4 as in eofa_chiral_action; phi a 4D canonical device buffer)
+ * followed by exactly niter >= 1 FP64 CG iterations on its Schur normal equations from x = 0, with no host
+ * synchronisation and no convergence stop in between.  *rel (may be NULL) = |r_niter| / |r_0| of the normal
+ * residual.  The solution is discarded.  Synchronises the stream.
+ */
+eofa_status eofa_cg_block(eofa_ctx *ctx, int chir, double m3, double m4, const void *phi, int niter, double *rel);
 
 /* Graph replays since the context was created and the number of instantiated graphs it holds. */
 eofa_status eofa_graph_stats(eofa_ctx *ctx, long *replays, int *cached);

@@ -126,3 +126,29 @@ def loss_and_grad(rho, e, dims, params, relu=False, bf16=False, dtype=torch.floa
         Wg[:, :, CIN[l]:] = 0
         g[l * LSZ + WSZ + COUT[l]: (l + 1) * LSZ] = 0
     return 2.0 * half_sq.item() / torch.sum(T * T).item(), g
+
+
+def layer_terms(rho, e, dims, params, bf16=True, dtype=torch.float32):
+    """Per-layer operands of the weight gradient of one training pair (input rho / |rho|, target e / |rho|,
+    linear network): X[l] the layer inputs as the convolution reads them ([Ns][Lt][Lz][Ly][Lx/2][32]) and
+    dY[l] = d(|N - T|^2 / 2)/d(output of layer l).  The weight gradient of layer l is
+    sum over rows of dY[l][row][n] X[l][row + d][k] at tap d (see conv), its bias gradient sum dY[l][row][n]."""
+    r = odd_rows(rho, dims)
+    t = odd_rows(e, dims)
+    nrm = np.sqrt(np.sum(r * r))
+    p = torch.as_tensor(np.asarray(params), dtype=dtype)
+    T = torch.zeros(r.shape[:-1] + (32,), dtype=dtype)
+    T[..., :24] = torch.as_tensor(t / nrm, dtype=dtype)
+    x = torch.zeros(r.shape[:-1] + (32,), dtype=dtype)
+    x[..., :24] = torch.as_tensor(r / nrm, dtype=dtype)
+    x = _bf(x, bf16)
+    x.requires_grad_(True)
+    X, Y = [], []
+    for l, (W, b) in enumerate(layer_views(p)):
+        X.append(x)
+        y = conv(x, _bf(W, bf16), b)
+        Y.append(y)
+        x = _bf(y, bf16) if l < LAYERS - 1 else y
+    half_sq = 0.5 * torch.sum((x - T) ** 2)
+    dY = torch.autograd.grad(half_sq, Y)
+    return [v.detach() for v in X], [v.detach() for v in dY]

@@ -51,13 +51,17 @@ struct eofa_ctx {
     int pstride = 0;
     std::map<std::tuple<int, double, double>, SiteOp*> tabs;
     std::string err;
-    // hop timing
+    // device time of the FP64 CG iteration's kernels (eofa_kernel_timing): HIP events around each launch
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    struct Ev {
+        hipEvent_t a, b;
+        int k;
+    };
+    std::vector<Ev> ev_pool;
     size_t ev_used = 0;
-    double hop_ms = 0;
-    long hop_launches = 0;
-    double hop_bytes = 0;
+    double k_ms[EOFA_NKERN] = {};
+    long k_n[EOFA_NKERN] = {};
+    double k_bytes[EOFA_NKERN] = {};
     // learned preconditioner (see cnn.hip)
     struct Cnn {
         bool ready = false;
@@ -252,36 +256,44 @@ template <> HopArgs<float> hop_args<float>(eofa_ctx* ctx, int par) {
     return a;
 }
 
-template <typename R> void hop(eofa_ctx* ctx, bool dag, int mode, bool red, const HopArgs<R>& a, bool timed = false) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (timed && ctx->timing) {
-        if (ctx->ev_used == ctx->ev_pool.size()) {
-            hipEvent_t a0, a1;
-            HIPCHK(hipEventCreate(&a0));
-            HIPCHK(hipEventCreate(&a1));
-            ctx->ev_pool.push_back({a0, a1});
-        }
-        e0 = ctx->ev_pool[ctx->ev_used].first;
-        e1 = ctx->ev_pool[ctx->ev_used].second;
-        ctx->ev_used++;
-        HIPCHK(hipEventRecord(e0, ctx->st));
+// Algorithmic HBM bytes of one launch of CG-iteration kernel k in FP64: every spinor field the kernel reads or
+// writes counted once (12 Ns complex per 4D site), the 8 links of each output site once.
+double kernel_bytes(const eofa_ctx* ctx, int k) {
+    const double col = 12.0 * ctx->Ns * sizeof(cd), links = 8.0 * 9 * sizeof(cd);
+    const int fields[EOFA_NKERN] = {2, 4, 2, 4, 5};  // K1 in+out; K2 in, p, w, wt; K3; K4 in, w, r in/out; K5 x, p, r, x, p
+    return (double)ctx->g.Vh * (fields[k] * col + (k < 4 ? links : 0.0));
+}
+
+// Runs launch() (kernel launches on ctx->st) and, while timing is on and k >= 0, records events around it
+// for kernel class k.
+template <typename F> void timed(eofa_ctx* ctx, int k, F&& launch) {
+    if (k < 0 || !ctx->timing) { launch(); return; }
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        eofa_ctx::Ev e{nullptr, nullptr, 0};
+        HIPCHK(hipEventCreate(&e.a));
+        HIPCHK(hipEventCreate(&e.b));
+        ctx->ev_pool.push_back(e);
     }
-    HIPCHK(launch_hop<R>(ctx->Ns, dag, mode, red, a, ctx->st));
-    if (e1) {
-        HIPCHK(hipEventRecord(e1, ctx->st));
-        ctx->hop_launches++;
-        // algorithmic bytes: in + out spinors + links (8 per 4D site, shared by the Ns slices)
-        ctx->hop_bytes += (double)ctx->g.Vh * (2.0 * 12 * ctx->Ns * 2 * sizeof(R) + 8 * 9 * 2 * sizeof(R));
-    }
+    eofa_ctx::Ev& e = ctx->ev_pool[ctx->ev_used++];
+    e.k = k;
+    HIPCHK(hipEventRecord(e.a, ctx->st));
+    launch();
+    HIPCHK(hipEventRecord(e.b, ctx->st));
+    ctx->k_n[k]++;
+    ctx->k_bytes[k] += kernel_bytes(ctx, k);
+}
+
+template <typename R> void hop(eofa_ctx* ctx, bool dag, int mode, bool red, const HopArgs<R>& a, int k = -1) {
+    timed(ctx, k, [&] { HIPCHK(launch_hop<R>(ctx->Ns, dag, mode, red, a, ctx->st)); });
 }
 
 void collect_timing(eofa_ctx* ctx) {
-    if (!ctx->timing || ctx->ev_used == 0) return;
+    if (ctx->ev_used == 0) return;
     HIPCHK(hipStreamSynchronize(ctx->st));
     for (size_t i = 0; i < ctx->ev_used; i++) {
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[i].first, ctx->ev_pool[i].second));
-        ctx->hop_ms += ms;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev_pool[i].a, ctx->ev_pool[i].b));
+        ctx->k_ms[ctx->ev_pool[i].k] += ms;
     }
     ctx->ev_used = 0;
 }
@@ -340,33 +352,39 @@ template <typename R> std::vector<uintptr_t> graph_key(const eofa_ctx* ctx, int 
     return k;
 }
 
-// One CG iteration on Dhat^dag Dhat in storage/arithmetic type R (the four fused hops + BLAS).
+// One CG iteration on Dhat^dag Dhat in storage/arithmetic type R (the four fused hops + BLAS).  Once the
+// device has flagged convergence (SC_DONE) every kernel of later iterations exits at once, and SC_ITERS
+// counts the iterations that were applied, so blocks of iterations can run without host checks.  FP64
+// iterations are timed per kernel (K1..K5) while kernel timing is on.
 template <typename R>
 void cg_iteration(eofa_ctx* ctx, cpx<R>* x, cpx<R>* r, cpx<R>* p, cpx<R>* u, cpx<R>* w, cpx<R>* wt, cpx<R>* at,
                   const SiteOp* Ai, const SiteOp* Ad) {
+    const int k0 = sizeof(R) == 8 ? 0 : -EOFA_NKERN;  // kernel classes are timed in FP64 only
+    const double* done = ctx->scal + SC_DONE;
     {
         auto a = hop_args<R>(ctx, 0);
-        a.in = p; a.out = u; a.opA = Ai; a.cz = 1; a.caux = 0;
-        hop<R>(ctx, false, HM_SITE, false, a, sizeof(R) == 8);
+        a.in = p; a.out = u; a.opA = Ai; a.cz = 1; a.caux = 0; a.done = done;
+        hop<R>(ctx, false, HM_SITE, false, a, k0 + EOFA_K_HOP);
     }
     {
         auto a = hop_args<R>(ctx, 1);
         a.in = u; a.out = w; a.out2 = wt; a.aux = p; a.opA = Ai; a.opB = Ad; a.cz = (R)-0.25; a.caux = 1;
-        a.red = red_of(ctx, 0, EPI_CG_W);
-        hop<R>(ctx, false, HM_SCHUR_W, true, a);
+        a.red = red_of(ctx, 0, EPI_CG_W); a.done = done;
+        hop<R>(ctx, false, HM_SCHUR_W, true, a, k0 + EOFA_K_SCHUR_W);
     }
     {
         auto a = hop_args<R>(ctx, 0);
-        a.in = wt; a.out = at; a.opA = Ad; a.cz = 1; a.caux = 0;
-        hop<R>(ctx, true, HM_SITE, false, a);
+        a.in = wt; a.out = at; a.opA = Ad; a.cz = 1; a.caux = 0; a.done = done;
+        hop<R>(ctx, true, HM_SITE, false, a, k0 + EOFA_K_HOP_DAG);
     }
     {
         auto a = hop_args<R>(ctx, 1);
         a.in = at; a.out = r; a.aux = w; a.aux2 = r; a.cz = (R)-0.25; a.caux = 1;
-        a.red = red_of(ctx, 0, EPI_CG_R);
-        hop<R>(ctx, true, HM_SCHUR_Q, true, a);
+        a.red = red_of(ctx, 0, EPI_CG_R); a.done = done;
+        hop<R>(ctx, true, HM_SCHUR_Q, true, a, k0 + EOFA_K_SCHUR_Q);
     }
-    HIPCHK(launch_cg_xp<R>(x, p, r, ctx->scal, ctx->nh, ctx->st));
+    timed(ctx, k0 + EOFA_K_XP, [&] { HIPCHK(launch_cg_xp<R>(x, p, r, ctx->scal, ctx->nh, ctx->st)); });
+    HIPCHK(launch_sync_done(ctx->scal, 1, ctx->st));
 }
 
 // ------------------------------------------------------------------ FP64 CG on Dhat^dag Dhat
@@ -376,15 +394,12 @@ struct CgOut {
     bool converged = false;
 };
 
-// Solve Dhat x = bh (odd sites) to |r_normal| <= tol_n |r_normal,0|; x starts at zero.
-CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
-           bool graph = false) {
-    const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
-    const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+// r = Dhat^dag bh, p = r, |r|^2 -> SC_RR, SC_RR0 (EPI_CG_INIT also clears SC_DONE unless r = 0, SC_DONEX and
+// SC_ITERS); x = 0.  The stop threshold SC_TOL2 = tol2.
+void cg64_init(eofa_ctx* ctx, const Work64& W, const SiteOp* Ad, double tol2) {
     const size_t nh = ctx->nh;
-    CgOut o;
     HIPCHK(hipMemsetAsync(W.xcg, 0, nh * sizeof(cd), ctx->st));
-    HIPCHK(launch_scal_set(ctx->scal, SC_TOL2, tol_n * tol_n, -1, 0, -1, 0, ctx->st));
+    HIPCHK(launch_scal_set(ctx->scal, SC_TOL2, tol2, -1, 0, -1, 0, ctx->st));
     // r = Dhat^dag bh = bh - 1/4 g5 H_oe g5 A^{-dag} g5 H_eo g5 A^{-dag} bh ; p = r
     HIPCHK(launch_site<double>(ctx->Ns, true, W.bh, W.wt, Ad, ctx->g.Vh, ctx->st));
     {
@@ -399,35 +414,42 @@ CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
         hop<double>(ctx, true, HM_LIN, true, a);
     }
     HIPCHK(hipMemcpyAsync(W.p, W.r, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
+}
+
+// Solve Dhat x = bh (odd sites) to |r_normal| <= tol_n |r_normal,0|; x starts at zero.  The host looks at the
+// device scalars every check_every iterations; iterations past convergence inside a block are skipped on the
+// device, and the iteration count is the device's.  With graph, every full block is one graph replay.
+CgOut cg64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, int maxit, int check_every,
+           bool graph = false) {
+    const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+    const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
+    CgOut o;
+    cg64_init(ctx, W, Ad, tol_n * tol_n);
     o.applies = 1;
     sync_scal(ctx);
     if (ctx->hscal[SC_DONE] != 0.0) { o.converged = true; return o; }
     if (check_every <= 0) check_every = 1;
-    while (o.iters < maxit) {
+    int launched = 0;
+    while (launched < maxit) {
         // u = A^{-1} H_eo p ; w = Dhat p, wt = A^{-dag} w, |w|^2 -> alpha ; at = A^{-dag} g5 H_eo g5 wt ;
         // r -= alpha (w - g5 H_oe g5 at / 4), |r|^2 -> beta ; x += alpha p, p = r + beta p
-        if (graph && o.iters % check_every == 0 && o.iters + check_every <= maxit) {
-            graph_run(ctx, graph_key<double>(ctx, 1, check_every, {W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad}),
-                      [&] {
-                          for (int k = 0; k < check_every; k++)
-                              cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
-                      });
-            o.iters += check_every;
-            o.applies += 2 * check_every;
+        const int blk = std::min(check_every, maxit - launched);
+        if (graph && blk == check_every) {
+            graph_run(ctx, graph_key<double>(ctx, 1, blk, {W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad}), [&] {
+                for (int k = 0; k < blk; k++) cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
+            });
         } else {
-            cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
-            o.iters++;
-            o.applies += 2;
+            for (int k = 0; k < blk; k++) cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
         }
-        if (o.iters % check_every == 0 || o.iters == maxit) {
-            sync_scal(ctx);
-            double rr = ctx->hscal[SC_RR];
-            if (!std::isfinite(rr) || !std::isfinite(ctx->hscal[SC_ALPHA])) {
-                ctx->err = "CG breakdown (non-finite scalar)";
-                return o;
-            }
-            if (ctx->hscal[SC_DONE] != 0.0) { o.converged = true; break; }
+        launched += blk;
+        sync_scal(ctx);
+        o.iters = (int)ctx->hscal[SC_ITERS];
+        o.applies = 1 + 2 * o.iters;
+        if (!std::isfinite(ctx->hscal[SC_RR]) || !std::isfinite(ctx->hscal[SC_ALPHA])) {
+            ctx->err = "CG breakdown (non-finite scalar)";
+            return o;
         }
+        if (ctx->hscal[SC_DONE] != 0.0) { o.converged = true; break; }
     }
     return o;
 }
@@ -448,10 +470,10 @@ double norm2_half(eofa_ctx* ctx, const cd* v) {
     return ctx->hscal[SC_TMP + 9];
 }
 
-int auto_check_every_n(const eofa_ctx* ctx) {
-    const double sites = (double)ctx->nh;
-    return sites >= 4e6 ? 1 : (sites >= 1e6 ? 4 : 16);
-}
+// Iterations between host checks when the caller leaves it to the library.  Iterations past convergence
+// inside a block exit at once on the device, so a block costs at most a few launches of waste; 16 keeps the
+// host out of the loop and gives a captured graph 16 iterations at every volume.
+constexpr int kAutoCheckEvery = 16;
 
 // ------------------------------------------------------------------ mixed precision CG
 // FP64 normal residual r = Dhat^dag (bh - Dhat x) into W.r; returns |r|^2 (host sync).
@@ -516,30 +538,26 @@ CgOut cg_mixed(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_
         // inner FP32 iterations until |r|^2 <= max(delta^2, target) * rr (the last replaced residual)
         const double tol2 = std::max(delta * delta, tol_n * tol_n * rr0 / rr);
         HIPCHK(launch_scal_set(ctx->scal, SC_RR, rr, SC_RR0, rr, SC_TOL2, tol2, ctx->st));
-        HIPCHK(launch_scal_set(ctx->scal, SC_DONE, 0.0, -1, 0, -1, 0, ctx->st));
-        int inner = 0;
-        while (o.iters < maxit) {
-            if (graph && inner % check_every == 0 && o.iters + check_every <= maxit) {
-                graph_run(ctx, graph_key<float>(ctx, 2, check_every, {F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad}),
-                          [&] {
-                              for (int k = 0; k < check_every; k++)
-                                  cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
-                          });
-                o.iters += check_every;
-                inner += check_every;
-                o.applies += 2 * check_every;
+        HIPCHK(launch_scal_set(ctx->scal, SC_DONE, 0.0, SC_DONEX, 0.0, SC_ITERS, 0.0, ctx->st));
+        const int base = o.iters;
+        int launched = 0;
+        while (base + launched < maxit) {
+            const int blk = std::min(check_every, maxit - base - launched);
+            if (graph && blk == check_every) {
+                graph_run(ctx, graph_key<float>(ctx, 2, blk, {F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad}), [&] {
+                    for (int k = 0; k < blk; k++) cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
+                });
             } else {
-                cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
-                o.iters++;
-                inner++;
-                o.applies += 2;
+                for (int k = 0; k < blk; k++) cg_iteration<float>(ctx, F.x, F.r, F.p, F.u, F.w, F.wt, F.at, Ai, Ad);
             }
-            if (inner % check_every == 0) {
-                sync_scal(ctx);
-                if (!std::isfinite(ctx->hscal[SC_RR])) { ctx->err = "mixed CG breakdown"; return o; }
-                if (ctx->hscal[SC_DONE] != 0.0 || inner >= kMaxCycle) break;
-            }
+            launched += blk;
+            sync_scal(ctx);
+            const int inner = (int)ctx->hscal[SC_ITERS];
+            o.iters = base + inner;
+            if (!std::isfinite(ctx->hscal[SC_RR])) { ctx->err = "mixed CG breakdown"; return o; }
+            if (ctx->hscal[SC_DONE] != 0.0 || inner >= kMaxCycle) break;
         }
+        o.applies += 2 * (o.iters - base);
         // reliable update: x_hi += x_lo ; r = Dhat^dag (bh - Dhat x_hi) in FP64
         HIPCHK(launch_accum_f(W.xcg, F.x, nh, ctx->st));
         HIPCHK(hipMemsetAsync(F.x, 0, nh * sizeof(cpx<float>), ctx->st));
@@ -755,7 +773,7 @@ CgOut fgcr(eofa_ctx* ctx, const Work64& W, double mp, double mm, double tol_n, i
     HIPCHK(hipMemcpyAsync(W.bh, rr, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
     HIPCHK(hipMemcpyAsync(Z[0], W.xcg, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
     const double rel = std::sqrt(std::max(r2, 1e-300) / b2);
-    CgOut c = cg64(ctx, W, mp, mm, std::min(0.5, tol_n / rel), maxit - o.iters, auto_check_every_n(ctx));
+    CgOut c = cg64(ctx, W, mp, mm, std::min(0.5, tol_n / rel), maxit - o.iters, kAutoCheckEvery);
     HIPCHK(launch_axpby<double>(1.0, Z[0], 1.0, W.xcg, nh, nullptr, ctx->st));
     o.iters += c.iters;
     o.applies += c.applies;
@@ -830,20 +848,13 @@ CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double 
 
 SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P);
 
-int auto_check_every(const eofa_ctx* ctx, const eofa_solve_params& P) {
-    if (P.check_every > 0) return P.check_every;
-    // host polls cost ~10 us; poll every iteration once an iteration takes >~1 ms
-    double sites = (double)ctx->nh;
-    if (sites >= 4e6) return 1;
-    if (sites >= 1e6) return 4;
-    return 16;
-}
+int auto_check_every(const eofa_solve_params& P) { return P.check_every > 0 ? P.check_every : kAutoCheckEvery; }
 
 // Defect correction on D_T x = c with W.x holding the current solution and W.res = c - D_T x:
 // even-odd Krylov solves of the defect until ||c - D_T x|| / ||c|| <= tol.
 void refine(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P, double cn2, double rel,
             SolveOut& so) {
-    const int ce = auto_check_every(ctx, P);
+    const int ce = auto_check_every(P);
     so.relres = rel;
     eofa_solve_params Q = P;  // switched to plain FP64 CG if a correction fails to halve the defect
     for (int attempt = 0; attempt < 20; attempt++) {
@@ -885,6 +896,7 @@ SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, con
 // ------------------------------------------------------------------ multi-RHS batch
 struct Sys {
     int cycle = 0;      // iterations since the last residual replacement
+    int base = 0;       // iterations before the current cycle
     int stall = 0;      // consecutive reliable updates that failed to halve the residual norm
     double rr_last = 0; // |r|^2 at the last reliable update
     double mp = 0, mm = 0;
@@ -993,7 +1005,9 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
         const double tol2 = mixed ? std::max(delta * delta, tol_n * tol_n * sys[r].rr0 / rr) : tol_n * tol_n;
         double* S = sys_scal(ctx, r);
         HIPCHK(launch_scal_set(S, SC_RR, rr, SC_RR0, rr_ref, SC_TOL2, tol2, ctx->st));
-        HIPCHK(launch_scal_set(S, SC_DONE, 0.0, SC_DONEX, 0.0, -1, 0, ctx->st));
+        HIPCHK(launch_scal_set(S, SC_DONE, 0.0, SC_DONEX, 0.0, SC_ITERS, 0.0, ctx->st));
+        sys[r].base = sys[r].iters;  // SC_ITERS counts this cycle's iterations
+        sys[r].cycle = 0;
     };
     for (int r = 0; r < nr; r++) {
         Sys& y = sys[r];
@@ -1012,12 +1026,14 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
         else HIPCHK(hipMemcpyAsync(y.p, y.r, nb, hipMemcpyDeviceToDevice, ctx->st));
         arm(r, rr, rr);
     }
+    // blocks of ce iterations between host checks; each system counts its applied iterations on the device
     int it = 0;
     while (it < maxit) {
         bool all = true;
         for (const Sys& y : sys) all &= y.conv;
         if (all) break;
-        if (graph && it % ce == 0 && it + ce <= maxit) {
+        const int blk = std::min(ce, maxit - it);
+        if (graph && blk == ce) {
             std::vector<uintptr_t> key = graph_key<R>(ctx, H ? 4 : 3, ce, {}, H);
             for (const Sys& y : sys)
                 for (const void* q : {(const void*)y.Ai, (const void*)y.Ad, (const void*)y.x, (const void*)y.r,
@@ -1027,23 +1043,21 @@ void cg_batch(eofa_ctx* ctx, const Work64& W, std::vector<Sys>& sys, double tol_
             graph_run(ctx, std::move(key), [&] {
                 for (int k = 0; k < ce; k++) cg_iteration_mr<R, H>(ctx, sys);
             });
-            it += ce;
-            for (Sys& y : sys) if (!y.conv) { y.iters += ce; y.cycle += ce; }
         } else {
-            cg_iteration_mr<R, H>(ctx, sys);
-            it++;
-            for (Sys& y : sys) if (!y.conv) { y.iters++; y.cycle++; }
+            for (int k = 0; k < blk; k++) cg_iteration_mr<R, H>(ctx, sys);
         }
-        if (it % ce && it < maxit) continue;
+        it += blk;
         sync_scal_batch(ctx, nr);
         for (int r = 0; r < nr; r++) {
             Sys& y = sys[r];
             const double* hs = ctx->hscal + BATCH_OFF + r * SC_N;
-            if (y.conv || (hs[SC_DONE] == 0.0 && !(mixed && y.cycle >= kMaxCycle))) continue;
+            if (y.conv) continue;
+            y.cycle = (int)hs[SC_ITERS];
+            y.iters = y.base + y.cycle;
+            if (hs[SC_DONE] == 0.0 && !(mixed && y.cycle >= kMaxCycle)) continue;
             if (!std::isfinite(hs[SC_RR])) { ctx->err = "batched CG breakdown"; y.conv = true; continue; }
             if (!mixed) { y.conv = true; HIPCHK(hipMemcpyAsync(y.xhi, y.x, nb, hipMemcpyDeviceToDevice, ctx->st)); continue; }
             // reliable update of system r (its delta target reached, or its cycle cut at kMaxCycle)
-            y.cycle = 0;
             HIPCHK(launch_accum_f(y.xhi, (const cpx<float>*)y.x, ctx->nh, ctx->st));
             HIPCHK(hipMemsetAsync(y.x, 0, nb, ctx->st));
             double rr = normal_residual64(ctx, W, y.xhi, y.bh, y.Ai, y.Ad);
@@ -1200,24 +1214,12 @@ eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo
     return EOFA_OK;
 }
 
-// n chiral actions through the multi-RHS path, in groups of up to NRMAX systems.
-eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const double* m3, const double* m4,
-                              const double* mo, const void* const* phi, void* const* out, const int* accumulate,
-                              double* S, const eofa_solve_params* P, eofa_solve_info* info) {
-    check_params(ctx, P);
-    for (int j = 0; j < n; j++) check_action(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j]);
-    if ((n <= 1 && P->prec != EOFA_MIXED_FP16) || ctx->Ns < 8 || P->pc != EOFA_PC_NONE) {
-        eofa_status worst = EOFA_OK;
-        for (int j = 0; j < n; j++) {
-            double sj = 0;
-            eofa_status a = chiral_impl(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j], accumulate ? accumulate[j] : 0,
-                                        &sj, P, info ? &info[j] : nullptr);
-            if (S) S[j] = sj;
-            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
-            if (a != EOFA_OK) worst = a;
-        }
-        return worst;
-    }
+// n 5D systems D_T(mp[j], mm[j]) x_j = c_j through the multi-RHS path, in groups of up to NRMAX systems:
+// fill_c(W, j) writes c_j into W.c; done(W, j, so) consumes the solution in W.x once the FP64 defect
+// correction has brought it to tol.
+template <typename FillC, typename Done>
+eofa_status batch_solve(eofa_ctx* ctx, int n, const double* mp, const double* mm, const eofa_solve_params* P,
+                        eofa_solve_info* info, FillC&& fill_c, Done&& done) {
     ensure_ws(ctx, needed_bytes(ctx, P, n));
     ensure_partials_mr(ctx);
     Work64 W = carve64(ctx);
@@ -1230,16 +1232,16 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
         for (int r = 0; r < nr; r++) {
             const int j = g0 + r;
             Sys& y = sys[r];
-            y.mp = m3[j];
-            y.mm = m4[j];
+            y.mp = mp[j];
+            y.mm = mm[j];
             y.Ai = site_tab(ctx, SK_AINV, y.mp, y.mm);
             y.Ad = site_tab(ctx, SK_AINV_DAG, y.mp, y.mm);
-            make_source(ctx, W, chir[j], phi[j]);
+            fill_c(W, j);
             REQUIRE(std::isfinite(norm2_64(ctx, W.c)), EOFA_EINVAL, "source has non-finite entries");
             prep_schur(ctx, W, y.Ai, y.bh);
         }
         const double tol_n = 0.25 * P->tol;
-        const int ce = auto_check_every(ctx, *P);
+        const int ce = auto_check_every(*P);
         if (P->prec == EOFA_FP64) cg_batch<double>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
         else if (P->prec == EOFA_MIXED_FP16)
             cg_batch<float, true>(ctx, W, sys, tol_n, P->max_iter, ce, P->reliable_delta, P->use_graph != 0);
@@ -1250,7 +1252,7 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
             const int j = g0 + r;
             Sys& y = sys[r];
             auto t1 = std::chrono::steady_clock::now();
-            make_source(ctx, W, chir[j], phi[j]);
+            fill_c(W, j);
             const double cn2 = norm2_64(ctx, W.c);
             reconstruct(ctx, W, y.Ai, y.xhi);
             SolveOut so;
@@ -1259,9 +1261,7 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
             so.applies = 2 * y.iters + 2 * y.updates + 2;
             const double rel = cn2 > 0 ? std::sqrt(residual64(ctx, W, y.mp, y.mm) / cn2) : 0.0;
             refine(ctx, W, y.mp, y.mm, *P, cn2 > 0 ? cn2 : 1.0, rel, so);
-            const double s = combine(ctx, W, chir[j], action_k(chir[j], m3[j], m4[j], mo[j]), phi[j], out[j],
-                                     accumulate ? accumulate[j] : 0);
-            if (S) S[j] = s;
+            done(W, j, so);
             const double te = std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
             fill_info(info ? &info[j] : nullptr, so, tb + te);
             if (!so.ok) worst = EOFA_ENOCONV;
@@ -1270,6 +1270,62 @@ eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const doubl
     collect_timing(ctx);
     if (worst != EOFA_OK && ctx->err.empty()) ctx->err = "a batched solve did not reach tol within max_iter";
     return worst;
+}
+
+// Whether n systems under P go through the multi-RHS kernels (else one by one).
+bool use_batch(const eofa_ctx* ctx, int n, const eofa_solve_params* P) {
+    return !((n <= 1 && P->prec != EOFA_MIXED_FP16) || ctx->Ns < 8 || P->pc != EOFA_PC_NONE);
+}
+
+// n chiral actions through the multi-RHS path, in groups of up to NRMAX systems.
+eofa_status chiral_batch_impl(eofa_ctx* ctx, int n, const int* chir, const double* m3, const double* m4,
+                              const double* mo, const void* const* phi, void* const* out, const int* accumulate,
+                              double* S, const eofa_solve_params* P, eofa_solve_info* info) {
+    check_params(ctx, P);
+    for (int j = 0; j < n; j++) check_action(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j]);
+    if (!use_batch(ctx, n, P)) {
+        eofa_status worst = EOFA_OK;
+        for (int j = 0; j < n; j++) {
+            double sj = 0;
+            eofa_status a = chiral_impl(ctx, chir[j], m3[j], m4[j], mo[j], phi[j], out[j], accumulate ? accumulate[j] : 0,
+                                        &sj, P, info ? &info[j] : nullptr);
+            if (S) S[j] = sj;
+            if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+            if (a != EOFA_OK) worst = a;
+        }
+        return worst;
+    }
+    return batch_solve(
+        ctx, n, m3, m4, P, info, [&](const Work64& W, int j) { make_source(ctx, W, chir[j], phi[j]); },
+        [&](const Work64& W, int j, const SolveOut&) {
+            const double s = combine(ctx, W, chir[j], action_k(chir[j], m3[j], m4[j], mo[j]), phi[j], out[j],
+                                     accumulate ? accumulate[j] : 0);
+            if (S) S[j] = s;
+        });
+}
+
+// H_T(mp, mm) x5 = b5 on canonical 5D fields: c = R5 gamma_5 b, D_T x = c.
+eofa_status solve_ht_impl(eofa_ctx* ctx, double mp, double mm, const void* b5, void* x5, const eofa_solve_params* P,
+                          eofa_solve_info* info) {
+    check_params(ctx, P);
+    REQUIRE(b5 && x5 && b5 != x5, EOFA_EINVAL, "bad field pointers");
+    REQUIRE(mp > 0 && mp <= 1 && mm > 0 && mm <= 1, EOFA_EINVAL, "masses must lie in (0, 1]");
+    auto t0 = std::chrono::steady_clock::now();
+    ensure_ws(ctx, needed_bytes(ctx, P));
+    Work64 W = carve64(ctx);
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_pack5<double>((const cd*)b5, W.c.h[par], ctx->g, par, ctx->Ns, 1, ctx->st));
+    SolveOut so = solve_dt(ctx, W, mp, mm, *P);
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_unpack5<double>(W.x.h[par], (cd*)x5, ctx->g, par, ctx->Ns, 0, ctx->st));
+    HIPCHK(hipStreamSynchronize(ctx->st));
+    collect_timing(ctx);
+    fill_info(info, so, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    if (!so.ok) {
+        if (ctx->err.empty()) ctx->err = "solve did not reach tol within max_iter";
+        return EOFA_ENOCONV;
+    }
+    return EOFA_OK;
 }
 
 // nrep launches of the fused hop (A_T^{-1} epilogue) alternating parities on workspace buffers,
@@ -1377,13 +1433,18 @@ template <typename R> struct ApplyBufs {
     cpx<R>* in[2];
     cpx<R>* out[2];
     cpx<R> *u, *w, *wt, *at;
+    const SiteOp* tab[4];  // site-operator tables by SiteKind for (mp, mm); a null entry is taken from site_tab
+    double* partials;      // reduction buffers of the Schur kernels (null: the context's)
+    double* scal;
 };
 
-// out = op(in) on canonical 5D fields, in storage/arithmetic type R.
+// out = op(in) on canonical 5D fields, in storage/arithmetic type R.  Every step is a kernel launch on
+// ctx->st (no memset or copy nodes, no allocation once the tables B.tab are given).
 template <typename R>
 void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out, const ApplyBufs<R>& B) {
     const int Ns = ctx->Ns;
     const size_t nh = ctx->nh;
+    auto tab = [&](SiteKind k) { return B.tab[k] ? B.tab[k] : site_tab(ctx, k, mp, mm); };
     for (int par = 0; par < 2; par++) HIPCHK(launch_pack5<R>(in, B.in[par], ctx->g, par, Ns, 0, ctx->st));
     switch (op) {
     case EOFA_OP_DW:
@@ -1392,7 +1453,7 @@ void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out
     case EOFA_OP_DT_DAG:
     case EOFA_OP_HT: {
         const bool dag = (op == EOFA_OP_DT_DAG);
-        const SiteOp* M = site_tab(ctx, dag ? SK_M_DAG : SK_M, mp, mm);
+        const SiteOp* M = tab(dag ? SK_M_DAG : SK_M);
         for (int par = 0; par < 2; par++) {
             auto a = hop_args<R>(ctx, par);
             a.in = B.in[1 - par]; a.self = B.in[par]; a.out = B.out[par]; a.opA = M; a.cz = 1; a.caux = 0;
@@ -1402,14 +1463,14 @@ void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out
         break;
     }
     case EOFA_OP_AT_INV: {
-        const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
+        const SiteOp* Ai = tab(SK_AINV);
         for (int par = 0; par < 2; par++) HIPCHK(launch_site<R>(Ns, false, B.in[par], B.out[par], Ai, ctx->g.Vh, ctx->st));
         break;
     }
     default: {  // SCHUR, SCHUR_DAG, SCHUR_NORMAL
-        const SiteOp* Ai = site_tab(ctx, SK_AINV, mp, mm);
-        const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, mp, mm);
-        HIPCHK(hipMemsetAsync(B.out[0], 0, nh * sizeof(cpx<R>), ctx->st));
+        const SiteOp* Ai = tab(SK_AINV);
+        const SiteOp* Ad = tab(SK_AINV_DAG);
+        HIPCHK(launch_fill0(B.out[0], nh * sizeof(cpx<R>), ctx->st));
         const cpx<R>* src = B.in[1];
         if (op != EOFA_OP_SCHUR_DAG) {
             auto a = hop_args<R>(ctx, 0);
@@ -1418,9 +1479,10 @@ void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out
             auto b = hop_args<R>(ctx, 1);
             b.in = B.u; b.out = B.w; b.out2 = B.wt; b.aux = src; b.opA = Ai; b.opB = Ad; b.cz = (R)-0.25; b.caux = 1;
             b.red = red_of(ctx, SC_TMP + 7, EPI_STORE);
+            if (B.partials) { b.red.partials = B.partials; b.red.scal = B.scal; }
             hop<R>(ctx, false, HM_SCHUR_W, true, b);
             if (op == EOFA_OP_SCHUR) {
-                HIPCHK(hipMemcpyAsync(B.out[1], B.w, nh * sizeof(cpx<R>), hipMemcpyDeviceToDevice, ctx->st));
+                HIPCHK(launch_copy(B.out[1], B.w, nh * sizeof(cpx<R>), ctx->st));
                 break;
             }
             src = B.w;
@@ -1438,6 +1500,13 @@ void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out
     // H_T = gamma_5 R5 D_T reflects in s and flips the lower spins on the way out
     for (int par = 0; par < 2; par++)
         HIPCHK(launch_unpack5<R>(B.out[par], out, ctx->g, par, Ns, op == EOFA_OP_HT ? 1 : 0, ctx->st));
+}
+
+void check_apply(eofa_ctx* ctx, int op, const void* in, const void* out, int prec) {
+    REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+    REQUIRE(in && out && in != out, EOFA_EINVAL, "bad field pointers");
+    REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be EOFA_FP64 or EOFA_MIXED_FP32");
+    REQUIRE(op >= EOFA_OP_DW && op <= EOFA_OP_SCHUR_NORMAL, EOFA_EINVAL, "unknown op");
 }
 
 }  // namespace
@@ -1599,46 +1668,57 @@ eofa_status eofa_hinv_batch(eofa_ctx* ctx, int n, const double* m_lo, const doub
 
 eofa_status eofa_solve_ht(eofa_ctx* ctx, double m_plus, double m_minus, const void* b5, void* x5,
                           const eofa_solve_params* params, eofa_solve_info* info) {
+    return guarded(ctx, [&]() { return solve_ht_impl(ctx, m_plus, m_minus, b5, x5, params, info); });
+}
+
+eofa_status eofa_solve_ht_batch(eofa_ctx* ctx, int n, const double* m_plus, const double* m_minus,
+                                const void* const* b5, void* const* x5, const eofa_solve_params* params,
+                                eofa_solve_info* info) {
     return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(n >= 0 && m_plus && m_minus && b5 && x5, EOFA_EINVAL, "bad batch arguments");
         check_params(ctx, params);
-        REQUIRE(b5 && x5 && b5 != x5, EOFA_EINVAL, "bad field pointers");
-        REQUIRE(m_plus > 0 && m_plus <= 1 && m_minus > 0 && m_minus <= 1, EOFA_EINVAL, "masses must lie in (0, 1]");
-        auto t0 = std::chrono::steady_clock::now();
-        ensure_ws(ctx, needed_bytes(ctx, params));
-        Work64 W = carve64(ctx);
-        // c = R5 gamma_5 b, then D_T x = c
-        for (int par = 0; par < 2; par++)
-            HIPCHK(launch_pack5<double>((const cd*)b5, W.c.h[par], ctx->g, par, ctx->Ns, 1, ctx->st));
-        SolveOut so = solve_dt(ctx, W, m_plus, m_minus, *params);
-        for (int par = 0; par < 2; par++)
-            HIPCHK(launch_unpack5<double>(W.x.h[par], (cd*)x5, ctx->g, par, ctx->Ns, 0, ctx->st));
-        HIPCHK(hipStreamSynchronize(ctx->st));
-        collect_timing(ctx);
-        fill_info(info, so, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-        if (!so.ok) {
-            if (ctx->err.empty()) ctx->err = "solve did not reach tol within max_iter";
-            return EOFA_ENOCONV;
+        for (int j = 0; j < n; j++) {
+            REQUIRE(b5[j] && x5[j] && b5[j] != x5[j], EOFA_EINVAL, "bad field pointers");
+            REQUIRE(m_plus[j] > 0 && m_plus[j] <= 1 && m_minus[j] > 0 && m_minus[j] <= 1, EOFA_EINVAL,
+                    "masses must lie in (0, 1]");
         }
-        return EOFA_OK;
+        if (!use_batch(ctx, n, params)) {
+            eofa_status worst = EOFA_OK;
+            for (int j = 0; j < n; j++) {
+                eofa_status a = solve_ht_impl(ctx, m_plus[j], m_minus[j], b5[j], x5[j], params, info ? &info[j] : nullptr);
+                if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+                if (a != EOFA_OK) worst = a;
+            }
+            return worst;
+        }
+        const eofa_status st = batch_solve(
+            ctx, n, m_plus, m_minus, params, info,
+            [&](const Work64& W, int j) {
+                for (int par = 0; par < 2; par++)
+                    HIPCHK(launch_pack5<double>((const cd*)b5[j], W.c.h[par], ctx->g, par, ctx->Ns, 1, ctx->st));
+            },
+            [&](const Work64& W, int j, const SolveOut&) {
+                for (int par = 0; par < 2; par++)
+                    HIPCHK(launch_unpack5<double>(W.x.h[par], (cd*)x5[j], ctx->g, par, ctx->Ns, 0, ctx->st));
+            });
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        return st;
     });
 }
 
 eofa_status eofa_apply(eofa_ctx* ctx, int op, double m_plus, double m_minus, const void* in, void* out,
                        eofa_precision prec) {
     return guarded(ctx, [&]() -> eofa_status {
-        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
-        REQUIRE(in && out && in != out, EOFA_EINVAL, "bad field pointers");
-        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be EOFA_FP64 or EOFA_MIXED_FP32");
-        REQUIRE(op >= EOFA_OP_DW && op <= EOFA_OP_SCHUR_NORMAL, EOFA_EINVAL, "unknown op");
+        check_apply(ctx, op, in, out, prec);
         eofa_solve_params P{1e-10, 1, prec, EOFA_PC_NONE, 0, 0, 0};
         ensure_ws(ctx, needed_bytes(ctx, &P));
         if (prec == EOFA_FP64) {
             Work64 W = carve64(ctx);
-            ApplyBufs<double> B{{W.x.h[0], W.x.h[1]}, {W.res.h[0], W.res.h[1]}, W.u, W.w, W.wt, W.at};
+            ApplyBufs<double> B{{W.x.h[0], W.x.h[1]}, {W.res.h[0], W.res.h[1]}, W.u, W.w, W.wt, W.at, {}, nullptr, nullptr};
             apply_op<double>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
         } else {
             Work32 F = carve32(ctx);
-            ApplyBufs<float> B{{F.x, F.r}, {F.e0, F.e1}, F.u, F.w, F.wt, F.at};
+            ApplyBufs<float> B{{F.x, F.r}, {F.e0, F.e1}, F.u, F.w, F.wt, F.at, {}, nullptr, nullptr};
             apply_op<float>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
         }
         HIPCHK(hipStreamSynchronize(ctx->st));
@@ -1654,23 +1734,43 @@ eofa_status eofa_graph_stats(eofa_ctx* ctx, long* replays, int* cached) {
     });
 }
 
-eofa_status eofa_hop_timing(eofa_ctx* ctx, int enable, double* ms, long* launches, double* bytes) {
+eofa_status eofa_kernel_timing(eofa_ctx* ctx, int enable, int reset, eofa_kernel_stats* stats) {
     return guarded(ctx, [&]() -> eofa_status {
         collect_timing(ctx);
+        if (reset)
+            for (int k = 0; k < EOFA_NKERN; k++) { ctx->k_ms[k] = 0; ctx->k_n[k] = 0; ctx->k_bytes[k] = 0; }
         ctx->timing = enable != 0;
-        if (ms) *ms = ctx->hop_ms;
-        if (launches) *launches = ctx->hop_launches;
-        if (bytes) *bytes = ctx->hop_bytes;
+        if (stats)
+            for (int k = 0; k < EOFA_NKERN; k++) {
+                stats->ms[k] = ctx->k_ms[k];
+                stats->launches[k] = ctx->k_n[k];
+                stats->bytes[k] = ctx->k_bytes[k];
+            }
         return EOFA_OK;
     });
 }
 
-eofa_status eofa_hop_timing_reset(eofa_ctx* ctx) {
+eofa_status eofa_cg_block(eofa_ctx* ctx, int chir, double m3, double m4, const void* phi, int niter, double* rel) {
     return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+        REQUIRE(niter >= 1, EOFA_EINVAL, "niter must be >= 1");
+        REQUIRE(chir == 1 || chir == -1, EOFA_EINVAL, "chir must be +1 or -1");
+        REQUIRE(phi != nullptr, EOFA_EINVAL, "null field pointer");
+        for (double m : {m3, m4}) REQUIRE(m > 0 && m <= 1, EOFA_EINVAL, "masses must lie in (0, 1]");
+        eofa_solve_params P{1e-10, 1, EOFA_FP64, EOFA_PC_NONE, 0, 0, 0};
+        ensure_ws(ctx, needed_bytes(ctx, &P));
+        Work64 W = carve64(ctx);
+        const SiteOp* Ai = site_tab(ctx, SK_AINV, m3, m4);
+        const SiteOp* Ad = site_tab(ctx, SK_AINV_DAG, m3, m4);
+        make_source(ctx, W, chir, phi);
+        prep_schur(ctx, W, Ai, W.bh);
+        cg64_init(ctx, W, Ad, 0.0);  // threshold 0: the device never flags convergence
+        for (int k = 0; k < niter; k++) cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
+        sync_scal(ctx);
         collect_timing(ctx);
-        ctx->hop_ms = 0;
-        ctx->hop_launches = 0;
-        ctx->hop_bytes = 0;
+        const double rr = ctx->hscal[SC_RR], rr0 = ctx->hscal[SC_RR0];
+        REQUIRE(std::isfinite(rr), EOFA_ENOCONV, "CG breakdown (non-finite residual)");
+        if (rel) *rel = rr0 > 0 ? std::sqrt(rr / rr0) : 0.0;
         return EOFA_OK;
     });
 }
@@ -1881,12 +1981,15 @@ eofa_status eofa_training_pairs(eofa_ctx* ctx, double mp, double mm, unsigned lo
         double rr = normal_residual64(ctx, W, W.xcg, W.bh, Ai, Ad);
         HIPCHK(hipMemcpyAsync(W.p, W.r, nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
         HIPCHK(launch_scal_set(ctx->scal, SC_RR, rr, SC_RR0, rr, SC_DONE, 0.0, ctx->st));
+        HIPCHK(launch_scal_set(ctx->scal, SC_DONEX, 0.0, SC_ITERS, 0.0, -1, 0, ctx->st));
         int k = 0, snap = 0, next = 2;
-        const int ce = auto_check_every_n(ctx);
+        const int ce = kAutoCheckEvery;
         while (k < 100000) {
             cg_iteration<double>(ctx, W.xcg, W.r, W.p, W.u, W.w, W.wt, W.at, Ai, Ad);
             k++;
             if (k == next && snap < n) {
+                sync_scal(ctx);  // no snapshot of an iterate the device has stopped updating
+                if (ctx->hscal[SC_DONE] != 0.0) break;
                 HIPCHK(hipMemsetAsync(W.res.h[0], 0, nh * sizeof(cd), ctx->st));
                 HIPCHK(launch_unpack5<double>(W.res.h[0], (cd*)e5[snap], ctx->g, 0, ctx->Ns, 0, ctx->st));
                 HIPCHK(launch_unpack5<double>(W.xcg, (cd*)e5[snap], ctx->g, 1, ctx->Ns, 0, ctx->st));
@@ -1938,8 +2041,8 @@ void eofa_destroy(eofa_ctx* ctx) {
     if (ctx->scal) (void)hipFree(ctx->scal);
     if (ctx->hscal) (void)hipHostFree(ctx->hscal);
     for (auto& e : ctx->ev_pool) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
     }
     delete ctx;
 }

@@ -304,8 +304,9 @@ enum : int {
     SC_RR0 = 4,     // |r_0|^2 (stop reference)
     SC_DONE = 5,    // 1 when converged (read by graph replays)
     SC_TOL2 = 6,    // stop threshold on |r|^2 / |r_0|^2
-    SC_DONEX = 7,   // multi-RHS: the x/p update of the converged iteration has been applied
-    SC_TMP = 8,     // 8..31 free slots for norms
+    SC_DONEX = 7,   // the x/p update of the converged iteration has been applied (lags SC_DONE by one kernel)
+    SC_TMP = 8,     // 8..29 free slots for norms
+    SC_ITERS = 30,  // CG iterations applied since the counter was cleared (counted on the device)
     SC_N = 32
 };
 enum : int { EPI_STORE = 0, EPI_CG_W = 1, EPI_CG_R = 2, EPI_CG_INIT = 3 };
@@ -329,11 +330,13 @@ __device__ __forceinline__ void finish_partials(const double* partials, unsigned
     s = block_sum256(s, lds);
     if (threadIdx.x == 0) {
         switch (epi) {
-        case EPI_CG_W:          // s = |Dhat p|^2
+        case EPI_CG_W:          // s = |Dhat p|^2 (after convergence the hops were skipped: keep the scalars)
+            if (S[SC_DONE] != 0.0) break;
             S[SC_WW] = s;
             S[SC_ALPHA] = S[SC_RR] / s;
             break;
         case EPI_CG_R:          // s = |r_new|^2
+            if (S[SC_DONE] != 0.0) break;
             S[SC_BETA] = s / S[SC_RR];
             S[SC_RR] = s;
             if (s <= S[SC_TOL2] * S[SC_RR0]) S[SC_DONE] = 1.0;
@@ -342,6 +345,8 @@ __device__ __forceinline__ void finish_partials(const double* partials, unsigned
             S[SC_RR] = s;
             S[SC_RR0] = s;
             S[SC_DONE] = (s == 0.0) ? 1.0 : 0.0;
+            S[SC_DONEX] = S[SC_DONE];
+            S[SC_ITERS] = 0.0;
             break;
         default:
             S[slot] = s;

@@ -84,8 +84,11 @@ template <typename R> hipError_t launch_hop(int Ns, bool dag, int mode, bool red
 int tw_grid(const Geom& g, int Ns, const Sched& sc);
 template <typename R> hipError_t launch_site(int Ns, bool dag, const cpx<R>* in, cpx<R>* out, const SiteOp* op, int Vh,
                                              hipStream_t st);
-template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, const double* scal, size_t n,
+// x += alpha p ; p = r + beta p unless scal[SC_DONEX] is set (follow with launch_sync_done)
+template <typename R> hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, double* scal, size_t n,
                                               hipStream_t st);
+// for each of nr scalar blocks (stride SC_N): SC_ITERS += 1 if SC_DONEX is clear, then SC_DONEX = SC_DONE
+hipError_t launch_sync_done(double* scal, int nr, hipStream_t st);
 template <typename R> hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red,
                                               hipStream_t st);
 template <typename R> hipError_t launch_norm2(const cpx<R>* x, size_t n, const Red& red, hipStream_t st);
@@ -98,6 +101,11 @@ hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, 
 hipError_t launch_finish(const Red& r, unsigned nblocks, hipStream_t st);
 // dst[i] = host_vals[i], i < n <= 64 (values travel as kernel arguments: the host array may die at once)
 hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream_t st);
+// dst[i] = host_vals[i] for any n, in chunks of 64 values travelling as kernel arguments
+hipError_t launch_set_block(double* dst, size_t n, const double* host_vals, hipStream_t st);
+// bytes (a multiple of 8) of dst set to zero / copied from src, by kernels
+hipError_t launch_fill0(void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 // sets S[s_i] = v_i for the slots s_i >= 0 (stream-ordered, no host buffer)
 hipError_t launch_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2, hipStream_t st);
 hipError_t launch_convert_d2f(const cd* in, cpx<float>* out, size_t n, hipStream_t st);

@@ -1,6 +1,8 @@
 // gfx950 kernels of the EOFA / optimal-DWF solve path: the fused even-odd hop with its
 // site-local epilogues, BLAS-1 steps with deterministic FP64 reductions, and the
 // pack / source / combine kernels at the canonical boundary.
+#include <algorithm>
+
 #include "eofa_int.h"
 
 namespace eofa {
@@ -15,30 +17,17 @@ namespace eofa {
 //   HM_SCHUR_Q q = caux*aux + cz*z;  out = aux2 - alpha*q;  sum |out|^2 -> beta  (CG residual update)
 //   HM_DT      out = caux*aux + cz*((4-m0) self + A(self) - z/2)                (D_T, A = M or M^T)
 //   HM_DW      out = caux*aux + cz*((4-m0) self - z/2)                          (D_w on every slice)
-#ifndef HOP_FENCE
+// Scheduling fence between the directions of the hop: keeps the compiler from hoisting every neighbour load
+// to the top (which spills at 256 VGPRs in FP64).
 #define HOP_FENCE() __builtin_amdgcn_sched_barrier(0)
-#endif
-#ifndef HOP_LDS_LINKS
-#define HOP_LDS_LINKS 1
-#endif
 
 // Cache policy of the hop's outputs: they are not read again by the same launch, so they bypass the
 // caches that hold the re-read neighbour spinors.
-#ifndef HOP_NT_STORE
-#define HOP_NT_STORE 1
-#endif
 template <typename R> __device__ __forceinline__ void st_out(cpx<R>* p, const cpx<R>& v) {
-    if constexpr (HOP_NT_STORE) {
-        __builtin_nontemporal_store(v.x, &p->x);
-        __builtin_nontemporal_store(v.y, &p->y);
-    } else {
-        *p = v;
-    }
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
 }
-template <typename T> __device__ __forceinline__ void st_raw(T* p, const T& v) {
-    if constexpr (HOP_NT_STORE) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
+template <typename T> __device__ __forceinline__ void st_raw(T* p, const T& v) { __builtin_nontemporal_store(v, p); }
 
 // ---- FP16 storage of a Krylov half field (EOFA_MIXED_FP16): per (cb, s) column the 12 complex
 // components as binary16 (re, im) pairs in 3 blocks of 4 (16 bytes, one load per block):
@@ -176,32 +165,23 @@ __device__ __forceinline__ void hop_lds(cpx<R> z[12], const cpx<R>* __restrict__
                                         const int nb[8], int s, int Vh = 0) {
 #pragma unroll
     for (int j = 0; j < 12; j++) z[j] = {0, 0};
-    if constexpr (H) {
-        hop_mu<NS, DAG, 0, R, H>(z, in, sUl[0], sUl[4], nb, s, Vh);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 1, R, H>(z, in, sUl[1], sUl[5], nb, s, Vh);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 2, R, H>(z, in, sUl[2], sUl[6], nb, s, Vh);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 3, R, H>(z, in, sUl[3], sUl[7], nb, s, Vh);
-    } else {
-        hop_mu<NS, DAG, 0>(z, in, sUl[0], sUl[4], nb, s);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 1>(z, in, sUl[1], sUl[5], nb, s);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 2>(z, in, sUl[2], sUl[6], nb, s);
-        HOP_FENCE();
-        hop_mu<NS, DAG, 3>(z, in, sUl[3], sUl[7], nb, s);
-    }
+    hop_mu<NS, DAG, 0, R, H>(z, in, sUl[0], sUl[4], nb, s, Vh);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 1, R, H>(z, in, sUl[1], sUl[5], nb, s, Vh);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 2, R, H>(z, in, sUl[2], sUl[6], nb, s, Vh);
+    HOP_FENCE();
+    hop_mu<NS, DAG, 3, R, H>(z, in, sUl[3], sUl[7], nb, s, Vh);
 }
 
-// z = hop(in) at (cb, s).  With HOP_LDS_LINKS the workgroup first stages its sites' links in LDS.
-// more_stores runs once before the workgroup barrier that publishes the staged data.
+// z = hop(in) at (cb, s).  For Ns >= 8 the workgroup first stages its sites' links in LDS (each link is then
+// read once instead of once per slice); Ns = 4 reads them from global memory.  more_stores runs once before
+// the workgroup barrier that publishes the staged data.
 template <int NS, bool DAG, typename R, typename F>
 __device__ __forceinline__ void hop_all(cpx<R> z[12], const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ Uown,
                                         const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int s,
                                         F more_stores) {
-    if constexpr (HOP_LDS_LINKS && NS >= 8) {
+    if constexpr (NS >= 8) {
         __shared__ cpx<R> sU[256 / NS][8][9];
         stage_links<NS>(sU, Uown, Uoth, cb, nb, s, more_stores);
         hop_lds<NS, DAG>(z, in, sU[threadIdx.x / NS], nb, s);
@@ -251,9 +231,8 @@ __device__ __forceinline__ int tile_of(int b, int n, const Sched& sc, const Geom
     }
     return b;
 }
-#ifndef HOP_WAVES
-#define HOP_WAVES 2
-#endif
+// occupancy hint of the hop kernels: 2 workgroups of 256 lanes per CU (128 VGPRs would spill in FP64)
+constexpr int HOP_WAVES = 2;
 
 // The epilogue of the fused hop at (cb, s) given z = hop(in): stores out (and out2 for HM_SCHUR_W) when
 // valid and returns this lane's contribution to the reduced norm (0 unless RED).  opA / opB are the
@@ -469,11 +448,8 @@ __device__ __forceinline__ void tw_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9],
     HOP_FENCE();
 }
 
-#ifndef HOP_TW_WAVES
-#define HOP_TW_WAVES 1
-#endif
 template <int NS, bool DAG, int MODE, bool RED, typename R, bool XL>
-__global__ __launch_bounds__(256, HOP_TW_WAVES) void k_hop_tw(const HopArgs<R> a) {
+__global__ __launch_bounds__(256, 1) void k_hop_tw(const HopArgs<R> a) {
     if (a.done && *a.done != 0.0) return;
     __shared__ cpx<R> sU[256 / NS][8][9];
     __shared__ cpx<R> xl[XL ? 12 : 1][256];  // XL: the current slab's input columns of this segment
@@ -702,8 +678,14 @@ __global__ __launch_bounds__(256) void k_h2d(const void* __restrict__ in, cd* __
     }
 }
 
+// After the x/p update of an iteration: count it if it was applied, then let SC_DONEX catch up with SC_DONE
+// (the update of the converging iteration itself is applied; later ones are skipped).
 __global__ void k_sync_done(double* scal, int nr) {
-    if (threadIdx.x < nr) scal[threadIdx.x * SC_N + SC_DONEX] = scal[threadIdx.x * SC_N + SC_DONE];
+    if (threadIdx.x < nr) {
+        double* S = scal + threadIdx.x * SC_N;
+        if (S[SC_DONEX] == 0.0) S[SC_ITERS] += 1.0;
+        S[SC_DONEX] = S[SC_DONE];
+    }
 }
 
 // ===================================================================== site-local op only
@@ -728,11 +710,13 @@ __global__ __launch_bounds__(256) void k_site(const cpx<R>* __restrict__ in, cpx
 }
 
 // ===================================================================== BLAS-1
-// CG step after the residual update: x += alpha p ; p = r + beta p   (alpha, beta on device)
+// CG step after the residual update: x += alpha p ; p = r + beta p   (alpha, beta on device; skipped once
+// the update of the converging iteration has been applied)
 template <typename R>
 __global__ __launch_bounds__(256) void k_cg_xp(cpx<R>* __restrict__ x, cpx<R>* __restrict__ p,
                                                const cpx<R>* __restrict__ r, const double* __restrict__ scal,
                                                size_t n) {
+    if (scal[SC_DONEX] != 0.0) return;
     xp_chunk<R>(x, p, r, (R)scal[SC_ALPHA], (R)scal[SC_BETA], n);
 }
 
@@ -959,6 +943,15 @@ __global__ __launch_bounds__(256) void k_combine(const cd* __restrict__ phi, con
     finish_sum(red, block_sum256(acc, lds));
 }
 
+// dst = 0 / dst = src over n doubles (kernels rather than memset / memcpy nodes, so that a caller may capture
+// them in a graph)
+__global__ __launch_bounds__(256) void k_fill0(double* __restrict__ dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = 0.0;
+}
+__global__ __launch_bounds__(256) void k_copy(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 struct Vec64 {
     double v[64];
 };
@@ -1180,12 +1173,17 @@ template hipError_t launch_site<double>(int, bool, const cd*, cd*, const SiteOp*
 template hipError_t launch_site<float>(int, bool, const cpx<float>*, cpx<float>*, const SiteOp*, int, hipStream_t);
 
 template <typename R>
-hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, const double* scal, size_t n, hipStream_t st) {
+hipError_t launch_cg_xp(cpx<R>* x, cpx<R>* p, const cpx<R>* r, double* scal, size_t n, hipStream_t st) {
     hipLaunchKernelGGL((k_cg_xp<R>), dim3(xp_grid<R>(n)), dim3(256), 0, st, x, p, r, scal, n);
     return hipGetLastError();
 }
-template hipError_t launch_cg_xp<double>(cd*, cd*, const cd*, const double*, size_t, hipStream_t);
-template hipError_t launch_cg_xp<float>(cpx<float>*, cpx<float>*, const cpx<float>*, const double*, size_t, hipStream_t);
+template hipError_t launch_cg_xp<double>(cd*, cd*, const cd*, double*, size_t, hipStream_t);
+template hipError_t launch_cg_xp<float>(cpx<float>*, cpx<float>*, const cpx<float>*, double*, size_t, hipStream_t);
+
+hipError_t launch_sync_done(double* scal, int nr, hipStream_t st) {
+    hipLaunchKernelGGL(k_sync_done, dim3(1), dim3(64), 0, st, scal, nr);
+    return hipGetLastError();
+}
 
 template <typename R>
 hipError_t launch_axpby(R a, const cpx<R>* x, R b, cpx<R>* y, size_t n, const Red* red, hipStream_t st) {
@@ -1213,6 +1211,29 @@ hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream
     for (int i = 0; i < n; i++) v.v[i] = host_vals[i];
     hipLaunchKernelGGL(k_set_vec, dim3(1), dim3(64), 0, st, dst, n, v);
     return hipGetLastError();
+}
+
+hipError_t launch_fill0(void* dst, size_t bytes, hipStream_t st) {
+    if (bytes % sizeof(double)) return hipErrorInvalidValue;
+    const size_t n = bytes / sizeof(double);
+    if (n) hipLaunchKernelGGL(k_fill0, dim3(nblk(n)), dim3(256), 0, st, (double*)dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes % sizeof(double)) return hipErrorInvalidValue;
+    const size_t n = bytes / sizeof(double);
+    if (n) hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(256), 0, st, (double*)dst, (const double*)src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_block(double* dst, size_t n, const double* host_vals, hipStream_t st) {
+    for (size_t i = 0; i < n; i += 64) {
+        const int m = (int)std::min<size_t>(64, n - i);
+        hipError_t e = launch_set_vec(dst + i, m, host_vals + i, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_scal_set(double* S, int s0, double v0, int s1, double v1, int s2, double v2, hipStream_t st) {

@@ -38,6 +38,14 @@ class SolveParams(C.Structure):
                 ("reliable_delta", C.c_double), ("use_graph", C.c_int), ("check_every", C.c_int)]
 
 
+NKERN = 5
+KERNELS = ("hop", "schur_w", "hop_dag", "schur_q", "xp")  # K1 .. K5 of one FP64 CG iteration
+
+
+class KernelStats(C.Structure):
+    _fields_ = [("ms", C.c_double * NKERN), ("launches", C.c_long * NKERN), ("bytes", C.c_double * NKERN)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("op_applies", C.c_int), ("reliable_updates", C.c_int),
                 ("fell_back", C.c_int), ("true_rel_resid", C.c_double), ("seconds", C.c_double)]
@@ -76,9 +84,11 @@ def load():
         "eofa_hinv_batch": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double), PP, PP, C.POINTER(C.c_double),
                             C.POINTER(SolveParams), C.POINTER(SolveInfo)],
         "eofa_solve_ht": [P, D, D, P, P, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "eofa_solve_ht_batch": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double), PP, PP, C.POINTER(SolveParams),
+                                C.POINTER(SolveInfo)],
         "eofa_apply": [P, I, D, D, P, P, I],
-        "eofa_hop_timing": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_long), C.POINTER(C.c_double)],
-        "eofa_hop_timing_reset": [P],
+        "eofa_kernel_timing": [P, I, I, C.POINTER(KernelStats)],
+        "eofa_cg_block": [P, I, D, D, P, I, C.POINTER(C.c_double)],
         "eofa_set_precond": [P, C.POINTER(C.c_float), Z, I],
         "eofa_graph_stats": [P, C.POINTER(C.c_long), C.POINTER(C.c_int)],
         "eofa_cnn_init": [P, C.c_ulonglong, I],
@@ -106,10 +116,10 @@ def exported_symbols():
     """Names the library exports (for the ABI test)."""
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
-                        "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht",
+                        "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht", "eofa_solve_ht_batch",
                         "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
-                        "eofa_hop_timing", "eofa_graph_stats", "eofa_hop_timing_reset", "eofa_set_precond",
+                        "eofa_kernel_timing", "eofa_cg_block", "eofa_graph_stats", "eofa_set_precond",
                         "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
 
 
@@ -207,6 +217,36 @@ class Context:
         st = self.lib.eofa_solve_ht(self.h, float(mp), float(mm), _ptr(b), _ptr(x), C.byref(p), C.byref(info))
         self._check(st, "solve_ht")
         return x, info.as_dict()
+
+    def solve_ht_batch(self, systems, bs, p=None):
+        """systems: list of (m_plus, m_minus); bs: list of 5D sources; returns [(x, info)]."""
+        p = p or params()
+        n = len(systems)
+        bs = [self._c128(b, self.shape5) for b in bs]
+        xs = [self.torch.empty_like(b) for b in bs]
+        self._prep_ws(p, n)
+        mp = (C.c_double * n)(*[float(a[0]) for a in systems])
+        mm = (C.c_double * n)(*[float(a[1]) for a in systems])
+        pb = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+        px = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        info = (SolveInfo * n)()
+        st = self.lib.eofa_solve_ht_batch(self.h, n, mp, mm, pb, px, C.byref(p), info)
+        self._check(st, "solve_ht_batch")
+        return [(xs[j], info[j].as_dict()) for j in range(n)]
+
+    def set_workspace(self, buf):
+        """Hand the library a caller-owned device buffer (a torch tensor, kept alive here) as its workspace."""
+        self._use_ws = False
+        self._ws = buf
+        addr = buf.data_ptr()
+        self._check(self.lib.eofa_set_workspace(self.h, C.c_void_p(addr), buf.numel() * buf.element_size()),
+                    "set_workspace")
+
+    def workspace_size(self, p=None, nrhs=1):
+        n = C.c_size_t()
+        self._check(self.lib.eofa_workspace_size(self.h, C.byref(p or params()), int(nrhs), C.byref(n)),
+                    "workspace_size")
+        return n.value
 
     def chiral_action(self, chir, m3, m4, mo, phi, p=None):
         p = p or params()
@@ -380,10 +420,18 @@ class Context:
                     "training_pairs")
         return list(zip(rho[:made.value], e[:made.value]))
 
-    def hop_timing(self, enable=True):
-        ms, n, b = C.c_double(), C.c_long(), C.c_double()
-        self._check(self.lib.eofa_hop_timing(self.h, int(enable), C.byref(ms), C.byref(n), C.byref(b)), "hop_timing")
-        return dict(ms=ms.value, launches=n.value, bytes=b.value)
+    def kernel_timing(self, enable=True, reset=False):
+        """Per-kernel device time of the FP64 CG iterations: {name: dict(ms, launches, bytes)} for K1..K5."""
+        st = KernelStats()
+        self._check(self.lib.eofa_kernel_timing(self.h, int(enable), int(reset), C.byref(st)), "kernel_timing")
+        return {KERNELS[k]: dict(ms=st.ms[k], launches=st.launches[k], bytes=st.bytes[k]) for k in range(NKERN)}
 
-    def hop_timing_reset(self):
-        self._check(self.lib.eofa_hop_timing_reset(self.h), "hop_timing_reset")
+    def cg_block(self, chir, m3, m4, phi, niter):
+        """Source build + even-odd preparation of one chiral action, then exactly niter FP64 CG iterations;
+        returns |r_niter| / |r_0| of the normal residual."""
+        phi = self._c128(phi, self.shape4)
+        self._prep_ws(params())
+        rel = C.c_double()
+        self._check(self.lib.eofa_cg_block(self.h, int(chir), float(m3), float(m4), _ptr(phi), int(niter),
+                                           C.byref(rel)), "cg_block")
+        return rel.value

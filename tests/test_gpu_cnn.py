@@ -132,3 +132,142 @@ def test_trained_network_on_heldout_field():
         assert r["fgcr"]["true_rel_resid"] <= 1e-10 and r["fgcr"]["fell_back"] == 0
         print(f"  iterations CG/FGCR {r['iter_ratio']:.3f}, Dhat applications {r['apply_ratio']:.3f}, "
               f"time {r['time_ratio']:.3f}")
+
+
+# ---------------------------------------------------------------------------------------------------------------
+# Element-wise parity.  The network input is built so that its normalisation is exact (odd-site entries in
+# {0, +-1, +-2} with a sum of squares 4^m, so |v| is a power of two and v / |v| is exact in BF16 on both sides),
+# and one layer carries seeded random weights while the other three are exact channel maps (one centre tap of
+# ones, in-channel c + a -> out-channel c + b, zero bias), which pass BF16 values through unchanged.  Then the
+# GPU and the CPU reference can differ only by
+#   * the FP32 summation order of the random layer: at most gamma_K * S, S = sum over taps and channels of
+#     |W| |X| + |bias| (K = 81 * 32 terms, gamma_K <= K * 2^-24 ~ 2^-13), and
+#   * a hidden BF16 rounding that the two orders put on different sides of a rounding boundary (only when the
+#     random layer is a hidden one): at most one BF16 unit in the last place, 2^-7 |value|.
+# A wrong tap, a mis-wrapped boundary site or a wrong channel changes an output by a sizeable fraction of S,
+# far above both terms.  The weight gradient: the GPU rounds the output gradient of the last layer to BF16
+# before the weight-gradient GEMM (2^-8 relative, round to nearest) and sums rows in FP32 in another order,
+# and its forward output differs from the reference's by the summation-order term above, so
+# |g - g_ref| <= 2^-7 G with G = sum over rows of |dY| |X| at that tap and channel pair (twice the rounding
+# term); a wrong tap or channel pairing moves g by about G / sqrt(rows) (rows <= 2048 here), several times the
+# bound.  The bias gradient, the row sum of dY, is held to 2^-7 of the row sum of |dY| on the same grounds.
+
+def _exact_field(dims, Ns, seed):
+    """Canonical 5D field whose odd-site reals are 0, +-1 or +-2 with sum of squares 4^m (even sites 0)."""
+    rng = np.random.default_rng(seed)
+    Lx, Ly, Lz, Lt = dims
+    n = Ns * Lt * Lz * Ly * (Lx // 2) * 24
+    m = 0
+    while 4 ** m < n:
+        m += 1
+    n2 = -(-(4 ** m - n) // 3)          # entries of magnitude 2
+    n1 = 4 ** m - 4 * n2                 # entries of magnitude 1; the rest are 0
+    assert 0 <= n1 and n1 + n2 <= n
+    mag = np.zeros(n)
+    mag[:n1] = 1.0
+    mag[n1:n1 + n2] = 2.0
+    vals = rng.permutation(mag) * rng.choice([-1.0, 1.0], n)
+    assert np.sum(vals * vals) == 4.0 ** m
+    rows = vals.reshape(Ns, Lt, Lz, Ly, Lx // 2, 24)
+    return R.rows_to_canonical(rows, dims)
+
+
+def _sandwich_params(layer, a_in, b_out, seed):
+    """Layer `layer` random (seeded), the others exact channel maps: the map before it writes channel c to
+    c + a_in, the map after it reads channel c + b_out into c (c < 24)."""
+    rnd = IN.cnn_params(seed, scale=1.0).astype(np.float64)
+    p = np.zeros(R.NPARAM)
+    for l in range(R.LAYERS):
+        lo = l * R.LSZ
+        if l == layer:
+            p[lo:lo + R.LSZ] = rnd[lo:lo + R.LSZ]
+            W = p[lo:lo + R.WSZ].reshape(81, 32, 32)
+            W[:, R.COUT[l]:, :] = 0
+            W[:, :, R.CIN[l]:] = 0
+            continue
+        W = p[lo:lo + R.WSZ].reshape(81, 32, 32)
+        c = np.arange(24)
+        src = c + (b_out if l == layer + 1 else 0)
+        dst = c + (a_in if l == layer - 1 else 0)
+        W[40, dst, src] = 1.0
+    return p.astype(np.float32)
+
+
+def _sandwich_cases():
+    out = []
+    for l in range(4):
+        for a in ((0, 8) if l > 0 else (0,)):
+            for b in ((0, 8) if l < 3 else (0,)):
+                out.append((l, a, b))
+    return out
+
+
+# gathered kernel (6 x 4 x 4 x 4) and LDS-tiled kernel (8 x 4 x 4 x 4); every tile touches the periodic wrap
+EW_LATTICES = [((6, 4, 4, 4), 8), ((8, 4, 4, 4), 8)]
+
+
+@pytest.mark.parametrize("dims,Ns", EW_LATTICES, ids=lambda c: str(c))
+@pytest.mark.parametrize("layer,a,b", _sandwich_cases(), ids=lambda c: str(c))
+def test_forward_elementwise(dims, Ns, layer, a, b):
+    print(f"[gpu] cnn forward element-wise dims={dims} Ns={Ns} random layer {layer} maps ({a}, {b})", flush=True)
+    ctx, lat = ctx_and_oracle(dims, Ns)
+    p = _sandwich_params(layer, a, b, 70 + layer)
+    ctx.set_precond(p)
+    x = _exact_field(dims, Ns, 71)
+    got = ctx.cnn_apply(torch.as_tensor(x)).cpu().numpy()
+    odd = _odd(dims)
+    assert np.all(got[:, ~odd] == 0)
+    ref = R.apply(x, dims, p, bf16=True, dtype=torch.float64)
+    # S: the random layer on |X| with |W| and |bias| (input of the random layer = exact channel map of |x|/|x|)
+    pa = np.abs(p.astype(np.float64))
+    S = R.apply(np.abs(x.real) + 1j * np.abs(x.imag), dims, pa, bf16=True, dtype=torch.float64)  # all parts >= 0
+    g_ = R.odd_rows(got, dims)
+    r_ = R.odd_rows(ref, dims)
+    s_ = R.odd_rows(S, dims)
+    err = np.abs(g_ - r_)
+    bound = 2.0 ** -13 * s_ + (2.0 ** -7 * np.abs(r_) if layer < 3 else 0.0) + 1e-30
+    worst = float((err / bound).max())
+    print(f"  max |got - ref| = {err.max():.3e}, max |ref| = {np.abs(r_).max():.3e}, worst err / bound = {worst:.3f}, "
+          f"elements off by more than 2^-13 S: {int((err > 2.0 ** -13 * s_).sum())} of {err.size}")
+    assert worst <= 1.0
+    assert np.abs(r_).max() > 0.05 * s_.max()   # the random layer is visible in the output
+
+
+@pytest.mark.parametrize("dims,Ns", EW_LATTICES, ids=lambda c: str(c))
+@pytest.mark.parametrize("layer,a,b", _sandwich_cases(), ids=lambda c: str(c))
+def test_weight_gradient_elementwise(dims, Ns, layer, a, b):
+    print(f"[gpu] cnn gradient element-wise dims={dims} Ns={Ns} random layer {layer} maps ({a}, {b})", flush=True)
+    ctx, lat = ctx_and_oracle(dims, Ns)
+    p = _sandwich_params(layer, a, b, 80 + layer)
+    ctx.set_precond(p)
+    rho, e = _exact_field(dims, Ns, 81), _exact_field(dims, Ns, 82)
+    _, g = ctx.cnn_train_step(torch.as_tensor(rho), torch.as_tensor(e), lr=0.0, want_grad=True)
+    X, dY = R.layer_terms(rho, e, dims, p.astype(np.float64), dtype=torch.float64)
+    rows = X[0].numel() // 32
+    for l in range(R.LAYERS):
+        Xl, dYl = X[l].reshape(rows, 32), dY[l].reshape(rows, 32)
+        gw = np.zeros((81, 32, 32))
+        G = np.zeros((81, 32, 32))
+        for dt in (-1, 0, 1):
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        tap = R.tap_index(dt, dz, dy, dx)
+                        xs = torch.roll(X[l], shifts=(-dt, -dz, -dy, -dx), dims=(1, 2, 3, 4)).reshape(rows, 32)
+                        gw[tap] = (dYl.T @ xs).numpy()
+                        G[tap] = (dYl.abs().T @ xs.abs()).numpy()
+        gw[:, R.COUT[l]:, :] = 0
+        gw[:, :, R.CIN[l]:] = 0
+        got = g[l * R.LSZ: l * R.LSZ + R.WSZ].reshape(81, 32, 32).astype(np.float64)
+        bound = 2.0 ** -7 * G + 1e-12
+        worst = float((np.abs(got - gw) / bound).max())
+        gb = dYl.sum(0).numpy()
+        gb[R.COUT[l]:] = 0
+        gotb = g[l * R.LSZ + R.WSZ: (l + 1) * R.LSZ].astype(np.float64)
+        bb = 2.0 ** -7 * dYl.abs().sum(0).numpy() + 1e-12
+        worstb = float((np.abs(gotb - gb) / bb).max())
+        print(f"  layer {l}: weight grad max |g| {np.abs(gw).max():.3e}, worst err / bound {worst:.3f}; "
+              f"bias grad worst err / bound {worstb:.3f}")
+        assert worst <= 1.0 and worstb <= 1.0
+        if l == layer:
+            assert np.abs(gw).max() > 0  # the random layer's gradient is live

@@ -1,7 +1,8 @@
 """The other synthetic workloads at their full sizes: the 16^3 x 32 precision comparison and the
 24^3 x 48 multi-RHS batch (12 sources over 3 mass pairs = 24 systems, FP32 storage, hipGraph replay).
-Every solve must reach the FP64 true residual; one FP64 solve per workload is checked with the
-oracle's own H_T on the whole lattice, and the reduced-precision results against FP64 GPU solves."""
+Every solve must reach the FP64 true residual; solutions of each workload are checked with the oracle's own
+H_T on the whole lattice (one FP64 solve at 16^3 x 32, one batched FP32 solve per mass pair at 24^3 x 48), and
+the reduced-precision results against FP64 GPU solves."""
 import numpy as np
 import pytest
 import torch
@@ -69,3 +70,17 @@ def test_config3_batched_graph_fp32():
         r64 = ctx.hinv(phis[j], *pairs[j], E.params(tol=1e-10))
         assert relerr(res[j].out, r64.out.cpu().numpy()) < 1e-8
         assert abs(res[j].S - r64.S) <= 1e-9 * abs(r64.S)
+    del res, phis
+    # the same batched FP32 hipGraph path on 5D systems: one H_T per mass pair (the + system of each pair, the
+    # larger mass second), every solution checked with the oracle's own H_T on the whole lattice
+    systems = [(lo, hi) for lo, hi in cfg["pairs"]]
+    rng = np.random.default_rng(3100)
+    bs = [rng.standard_normal(lat.shape5) + 1j * rng.standard_normal(lat.shape5) for _ in systems]
+    out = ctx.solve_ht_batch(systems, [torch.from_numpy(b) for b in bs],
+                             E.params(tol=1e-10, prec=E.MIXED_FP32, use_graph=1))
+    for (x, info), b, (mp, mm) in zip(out, bs, systems):
+        res = lat.ht(x.cpu().numpy(), mp, mm) - b
+        rel = np.linalg.norm(res) / np.linalg.norm(b)
+        print(f"  H_T({mp}, {mm}): iters {info['iters']}, GPU residual {info['true_rel_resid']:.2e}, "
+              f"oracle residual {rel:.2e}")
+        assert info["true_rel_resid"] <= 1e-10 and rel <= 2e-10

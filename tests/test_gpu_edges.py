@@ -106,3 +106,44 @@ def test_frequent_replacement_still_converges(setup, prec):
     assert info["true_rel_resid"] <= 1e-10
     r = lat.ht(x.cpu().numpy(), 0.05, 1.0) - b.numpy()
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b.numpy())
+
+
+@pytest.mark.parametrize("case", ["omega_not_r5", "omega_negative", "odd_extent", "ns6", "m0", "tbc"])
+def test_create_rejects_bad_arguments(case):
+    """eofa_create: every malformed lattice or weight argument is EINVAL and no context is returned."""
+    from paper_1710_09621_amd import eofa as E
+    from paper_1710_09621_amd import inputs as IN
+    dims, Ns, m0, om, tbc = (4, 4, 4, 4), 8, 1.3, IN.optimal_omega(8), -1
+    if case == "omega_not_r5":
+        om = om.copy()
+        om[0] *= 1.001
+    elif case == "omega_negative":
+        om = om.copy()
+        om[2] = om[-3] = -om[2]
+    elif case == "odd_extent":
+        dims = (4, 5, 4, 4)
+    elif case == "ns6":
+        Ns, om = 6, IN.optimal_omega(6)
+    elif case == "m0":
+        m0 = 2.5
+    elif case == "tbc":
+        tbc = 0
+    with pytest.raises(E.EofaError) as ei:
+        E.Context(dims, Ns, m0, om, t_bc=tbc)
+    assert ei.value.status == E.EINVAL
+
+
+def test_too_small_workspace_is_enomem(setup):
+    """A caller-owned workspace below eofa_workspace_size is refused (ENOMEM), and the context recovers
+    once a large enough one is set."""
+    from paper_1710_09621_amd import eofa as E
+    ctx, lat = setup
+    p = E.params()
+    need = ctx.workspace_size(p)
+    ctx.set_workspace(torch.empty(need // 2, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(E.EofaError) as ei:
+        ctx.hinv(_phi(lat, 48), 0.05, 1.0, p)
+    assert ei.value.status == E.ENOMEM
+    ctx.set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
+    r = ctx.hinv(_phi(lat, 48), 0.05, 1.0, p)
+    assert all(i["true_rel_resid"] <= 1e-10 for i in r.info)

@@ -46,3 +46,35 @@ def test_graph_batch_is_bit_identical():
         for a, b in zip(r0, r1):
             assert torch.equal(a.out, b.out) and a.S == b.S
     assert ctx.graph_stats()["replays"] > 0
+
+
+@pytest.mark.parametrize("prec", ["FP64", "MIXED_FP32", "MIXED_FP16"])
+@pytest.mark.parametrize("batch", [False, True])
+def test_device_convergence_matches_every_iteration_check(prec, batch):
+    """Iterations after the device has flagged convergence are skipped on the device and the iteration
+    count is the device's: blocks of 16 iterations between host checks (eager and as graph replays) give
+    bitwise the solution and the iteration count of a host check after every iteration."""
+    from paper_1710_09621_amd import eofa as E
+    dims, Ns = (4, 4, 4, 8), 16
+    print(f"[gpu] device-side convergence prec={prec} batch={batch}", flush=True)
+    ctx, lat = ctx_and_oracle(dims, Ns)
+    pr = getattr(E, prec)
+    bs = [torch.as_tensor(rand5(lat, 60 + j)) for j in range(3)]
+    systems = [(0.01, 0.1), (0.1, 1.0), (1.0, 0.1)]
+
+    def run(**kw):
+        P = E.params(tol=1e-10, prec=pr, **kw)
+        if batch:
+            return ctx.solve_ht_batch(systems, bs, P)
+        return [ctx.solve_ht(b, *m, P) for b, m in zip(bs, systems)]
+
+    ref = run(check_every=1)
+    for kw in (dict(check_every=16), dict(check_every=16, use_graph=1), dict(check_every=5, use_graph=1)):
+        got = run(**kw)
+        for (x0, i0), (x1, i1) in zip(ref, got):
+            assert i1["iters"] == i0["iters"], (kw, i0, i1)
+            assert torch.equal(x0, x1), kw
+    for (x, i), b, m in zip(ref, bs, systems):
+        assert i["true_rel_resid"] <= 1e-10
+        r = lat.ht(x.cpu().numpy(), *m) - b.numpy()
+        assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(b.numpy())
