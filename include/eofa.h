@@ -162,6 +162,23 @@ eofa_status eofa_hinv_batch(eofa_ctx *ctx, int n, const double *m_lo, const doub
 eofa_status eofa_solve_ht(eofa_ctx *ctx, double m_plus, double m_minus, const void *b5, void *x5,
                           const eofa_solve_params *params, eofa_solve_info *info);
 
+/*
+ * eofa_apply for callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same operators, kernels and results as eofa_apply, but the
+ * intermediate half fields, the site-operator tables and the reduction buffers live in a static device array
+ * of 64 MiB that the library holds on every GPU it runs on until the process ends.  It calls no allocation
+ * routine, and no memset or memcpy: every step is a kernel launch on the context's stream, and it returns
+ * without synchronising the stream (out is ready once the stream has drained).  The context must have been
+ * created and its gauge field set beforehand (those calls allocate).  The array holds eight half fields
+ * (192 bytes in FP64, 96 in FP32, per 4D site of one parity and slice), four operator tables and the partial
+ * sums; a lattice that does not fit is refused with EOFA_EINVAL (in FP64 up to about 43,000 site-slices per
+ * parity, e.g. 8^4 with Ns = 16).  All calls on one GPU share the array and it keeps the last call's
+ * contents (every call writes what it reads): calls that overlap in time on one GPU (other streams, threads
+ * or contexts) race and give undefined results.
+ */
+eofa_status eofa_apply_static(eofa_ctx *ctx, int op, double m_plus, double m_minus, const void *in, void *out,
+                              eofa_precision prec);
+
 /* n systems H_T(m_plus[j], m_minus[j]) x5[j] = b5[j] solved together (the multi-RHS form of eofa_solve_ht; host
  * arrays of n device pointers to 5D canonical buffers, b5[j] != x5[j]).  Up to 8 systems share each launch
  * sequence, as in eofa_chiral_action_batch; info[j] per system (may be NULL). */

@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -28,8 +29,39 @@
 
 using namespace eofa;
 
+// ------------------------------------------------------------------ allocation-free scratch
+// Device memory of eofa_apply_static, for callers that cannot allocate: the intermediate half fields, the
+// site-operator tables and the reduction buffers of one operator application.  Every GPU the library runs on
+// holds its own copy until the process ends; host code reaches it only through the per-device address that
+// hipGetSymbolAddress returns (scratch_addr), never through the array's name.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (which must be current); resolved once per device.
+hipError_t scratch_addr(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return hipSuccess;
+}
+}  // namespace
+
 struct eofa_ctx {
     int L[4] = {0, 0, 0, 0};
+    int dev = 0;
+    void* scratch = nullptr;  // this device's address of the static scratch array
+    std::string scratch_err;
     int Ns = 0;
     double m0 = 0;
     int tbc = -1;
@@ -1543,6 +1575,14 @@ eofa_status eofa_create(eofa_ctx** out, const int dims[4], int Ns, double m0, co
         ctx->tbc = t_bc;
         ctx->omega.assign(omega_host, omega_host + Ns);
         ctx->st = (hipStream_t)hip_stream;
+        HIPCHK(hipGetDevice(&ctx->dev));
+        {   // the static scratch of eofa_apply_static; a failure here only disables that entry point
+            const hipError_t e = scratch_addr(ctx->dev, &ctx->scratch);
+            if (e != hipSuccess) {
+                ctx->scratch = nullptr;
+                ctx->scratch_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            }
+        }
         ctx->g = Geom{dims[0], dims[1], dims[2], dims[3], dims[0] / 2, (int)(V / 2)};
         ctx->nh = (size_t)(V / 2) * 12 * Ns;
         // one partial per block: hop kernels use <= nh / 256 blocks, grid-stride reductions <= 4096
@@ -1722,6 +1762,54 @@ eofa_status eofa_apply(eofa_ctx* ctx, int op, double m_plus, double m_minus, con
             apply_op<float>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
         }
         HIPCHK(hipStreamSynchronize(ctx->st));
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_apply_static(eofa_ctx* ctx, int op, double m_plus, double m_minus, const void* in, void* out,
+                              eofa_precision prec) {
+    return guarded(ctx, [&]() -> eofa_status {
+        check_apply(ctx, op, in, out, prec);
+        REQUIRE(ctx->scratch != nullptr, EOFA_ESTATE, "static scratch unavailable on this device: " + ctx->scratch_err);
+        const size_t rs = prec == EOFA_FP64 ? sizeof(cd) : sizeof(cpx<float>);
+        const size_t hb = align_up(ctx->nh * rs);
+        const size_t tb = align_up(sizeof(SiteOp));
+        const size_t nblocks = (ctx->nh + 255) / 256 + 4096;  // as the context's partials: >= any hop grid
+        const size_t pb = align_up(nblocks * sizeof(double)), sb = align_up(SC_N * sizeof(double));
+        const size_t need = 8 * hb + 4 * tb + pb + sb;
+        REQUIRE(need <= kStaticScratchBytes, EOFA_EINVAL,
+                "eofa_apply_static: this lattice needs " + std::to_string(need) + " bytes of scratch, more than the "
+                "static " + std::to_string(kStaticScratchBytes) + " (use eofa_apply)");
+        char* q = (char*)ctx->scratch;
+        auto take = [&](size_t n) { char* r = q; q += n; return r; };
+        void* h[8];
+        for (void*& v : h) v = take(hb);
+        // the site-operator tables this op reads, built on the host and written by kernels
+        const SiteOp* tabs[4] = {nullptr, nullptr, nullptr, nullptr};
+        const bool schur = op >= EOFA_OP_SCHUR, dt = op == EOFA_OP_DW || op == EOFA_OP_HOP || op == EOFA_OP_DT ||
+                                                        op == EOFA_OP_DT_DAG || op == EOFA_OP_HT;
+        const bool used[4] = {schur || op == EOFA_OP_AT_INV, schur, dt && op != EOFA_OP_DT_DAG, op == EOFA_OP_DT_DAG};
+        for (int k = 0; k < 4; k++) {
+            double* d = (double*)take(tb);
+            if (!used[k]) continue;
+            SiteOp host;
+            build_site_op(host, (SiteKind)k, ctx->Ns, ctx->m0, ctx->omega.data(), m_plus, m_minus);
+            HIPCHK(launch_set_block(d, sizeof(SiteOp) / sizeof(double), (const double*)&host, ctx->st));
+            tabs[k] = (const SiteOp*)d;
+        }
+        double* partials = (double*)take(pb);
+        double* scal = (double*)take(sb);
+        if (prec == EOFA_FP64) {
+            ApplyBufs<double> B{{(cd*)h[0], (cd*)h[1]}, {(cd*)h[2], (cd*)h[3]}, (cd*)h[4], (cd*)h[5], (cd*)h[6], (cd*)h[7],
+                                {tabs[0], tabs[1], tabs[2], tabs[3]}, partials, scal};
+            apply_op<double>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
+        } else {
+            using cf = cpx<float>;
+            ApplyBufs<float> B{{(cf*)h[0], (cf*)h[1]}, {(cf*)h[2], (cf*)h[3]}, (cf*)h[4], (cf*)h[5], (cf*)h[6], (cf*)h[7],
+                               {tabs[0], tabs[1], tabs[2], tabs[3]}, partials, scal};
+            apply_op<float>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
+        }
+        HIPCHK(hipGetLastError());
         return EOFA_OK;
     });
 }

@@ -87,6 +87,7 @@ def load():
         "eofa_solve_ht_batch": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double), PP, PP, C.POINTER(SolveParams),
                                 C.POINTER(SolveInfo)],
         "eofa_apply": [P, I, D, D, P, P, I],
+        "eofa_apply_static": [P, I, D, D, P, P, I],
         "eofa_kernel_timing": [P, I, I, C.POINTER(KernelStats)],
         "eofa_cg_block": [P, I, D, D, P, I, C.POINTER(C.c_double)],
         "eofa_set_precond": [P, C.POINTER(C.c_float), Z, I],
@@ -117,7 +118,7 @@ def exported_symbols():
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
                         "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht", "eofa_solve_ht_batch",
-                        "eofa_apply", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
+                        "eofa_apply", "eofa_apply_static", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
                         "eofa_kernel_timing", "eofa_cg_block", "eofa_graph_stats", "eofa_set_precond",
                         "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
@@ -206,6 +207,17 @@ class Context:
         self._prep_ws(params(prec=prec))
         self._check(self.lib.eofa_apply(self.h, OPS[op] if isinstance(op, str) else int(op), float(mp), float(mm),
                                         _ptr(x), _ptr(out), int(prec)), f"apply({op})")
+        return out
+
+    def apply_static(self, op, x, mp=1.0, mm=1.0, prec=FP64, out=None):
+        """eofa_apply_static: as apply, with no device allocation inside the call (the library's static
+        scratch); the caller provides out (allocated here when None).  Waits for the stream."""
+        x = self._c128(x, self.shape5)
+        if out is None:
+            out = self.torch.empty_like(x)
+        self._check(self.lib.eofa_apply_static(self.h, OPS[op] if isinstance(op, str) else int(op), float(mp),
+                                               float(mm), _ptr(x), _ptr(out), int(prec)), f"apply_static({op})")
+        self.torch.cuda.synchronize(self.device)
         return out
 
     def solve_ht(self, b, mp, mm, p=None):
