@@ -1,0 +1,163 @@
+"""Summaries of rocprofv3 output for profiles/ (run on the host after a profiled run).
+
+    python -m paper_1710_09621_amd.profile_summary trace  DIR BENCH_JSON OUT_MD  "COMMAND"
+    python -m paper_1710_09621_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT_JSON "FETCH_COMMAND" "WRITE_COMMAND"
+
+trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
+dominant kernel (the FP64 hop K1 of the schedule the bench picked), the average duration of its launches in
+the timed steps next to the bench's own HIP-event figure.
+
+traffic: HBM bytes per launch of the FP64 hop under each profiled schedule from two `rocprofv3 --pmc` passes
+of profile_hop.py (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+for k_site, which reads and writes exactly one FP64 half field; the result carries a hash of the kernel
+sources so that bench.py drops it once the kernels change.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_1710_09621_amd/csrc/kernels.hip", "paper_1710_09621_amd/csrc/eofa_dev.h",
+                  "paper_1710_09621_amd/csrc/eofa_int.h"]
+
+
+def _rows(pattern):
+    out = []
+    for path in sorted(glob.glob(pattern, recursive=True)):
+        with open(path, newline="") as f:
+            out += list(csv.DictReader(f))
+    return out
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(f"none of {names} in {list(row)}")
+
+
+def source_sha1():
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def hop_kernel_name(sched):
+    """Kernel-name prefix of the FP64 K1 hop (u = A_T^{-1} H_eo p, HM_SITE = 1) under schedule sched."""
+    if sched[0] == 5:
+        return "eofa::k_hop_tw<16, false, 1, false, double, true>"
+    if sched[0] == 3:
+        return "eofa::k_hop_tw<16, false, 1, false, double, false>"
+    return "eofa::k_hop<16, false, 1, false, double>"
+
+
+def trace(d, bench_json, out_md, command):
+    stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
+    kt = _rows(os.path.join(d, "**", "*kernel_trace.csv"))
+    with open(bench_json) as f:
+        b = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    sched = b["schedules"]["fp64"]
+    name = hop_kernel_name(sched)
+    total = sum(float(_col(r, "TotalDurationNs")) for r in stats)
+    stats.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
+    lines = [f"# FP64 CG iteration kernels on {b['config']['lattice']}, Ns = {b['config']['Ns']}: bench kernel trace", "",
+             "Command (repository root, GPU box):", "", f"    {command}", "",
+             f"The run: autotune of the hop schedules, {b['warmup']} warm-up and {b['steps']} timed steps; one step = "
+             f"{b['config']['workload'].split('; one step = ')[-1]}.", "",
+             "## Top kernels (rocprofv3 --stats, whole run)", "", "| kernel | calls | avg us | total % |",
+             "|---|---:|---:|---:|"]
+    for r in stats[:14]:
+        nm = _col(r, "Name", "KernelName", "Kernel_Name").replace("|", "\\|")
+        lines.append(f"| `{nm[:110]}` | {_col(r, 'Calls')} | {float(_col(r, 'AverageNs')) / 1e3:.1f} | "
+                     f"{100 * float(_col(r, 'TotalDurationNs')) / total:.2f} |")
+    # launches of the dominant kernel in time order; the last steps * niter are the timed steps' K1 launches
+    k1 = [r for r in kt if _col(r, "Kernel_Name", "KernelName", "Name").replace("void ", "").startswith(name)]
+    k1.sort(key=lambda r: int(_col(r, "Start_Timestamp")))
+    n_timed = b["steps"] * b["config"]["cg_iterations_per_step"]
+    dur = [(int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3 for r in k1]
+    timed = dur[-n_timed:]
+    avg = sum(timed) / len(timed)
+    alg = b["roofline"]["alg_bytes_per_launch"]
+    lines += ["", f"## Dominant kernel `{name}` (FP64 schedule {sched} picked by the autotuner)", "",
+              f"- launches in the run: {len(dur)} (autotune candidates and warm-up included)",
+              f"- launches in the timed steps: {n_timed}; their average duration in the trace: **{avg:.1f} us**",
+              f"- bench.py in the same run (HIP events around each launch): {b['roofline']['avg_launch_ms'] * 1e3:.1f} us, "
+              f"{b['value']:.0f} GB/s algorithmic ({alg / 1e9:.3f} GB per launch), frac {b['roofline']['frac']:.3f} of 8 TB/s",
+              f"- from the trace average: {alg / (avg * 1e-6) / 1e9:.0f} GB/s, frac {alg / (avg * 1e-6) / 8e12:.3f}", "",
+              "## One FP64 CG iteration (bench.py, HIP events)", "",
+              "| kernel | ms per launch | GB/s algorithmic |", "|---|---:|---:|"]
+    for k, v in b["cg_iteration"]["kernels"].items():
+        lines.append(f"| {k} | {v['ms']:.4f} | {v['gbs']:.0f} |")
+    it = b["cg_iteration"]
+    lines += [f"| whole iteration | {it['ms']:.3f} | {it['gbs']:.0f} (frac {it['frac']:.3f}) |", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    print(out_md, f"K1 trace avg {avg:.1f} us vs bench {b['roofline']['avg_launch_ms'] * 1e3:.1f} us")
+
+
+def _per_dispatch(d, counter):
+    """[(kernel name, value)] per dispatch in dispatch order."""
+    rows = _rows(os.path.join(d, "**", "*counter_collection.csv"))
+    out = {}
+    for r in rows:
+        if _col(r, "Counter_Name") != counter:
+            continue
+        did = int(_col(r, "Dispatch_Id"))
+        nm = _col(r, "Kernel_Name")
+        out.setdefault(did, [nm, 0.0])[1] += float(_col(r, "Counter_Value"))
+    return [tuple(out[k]) for k in sorted(out)]
+
+
+def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, dims=(32, 32, 32, 64), Ns=16, nrep=3):
+    import re
+    scheds = [s.split()[0] for s in re.findall(r"--sched (\S+)", fetch_cmd)]
+    f = _per_dispatch(fetch_dir, "FETCH_SIZE")
+    w = _per_dispatch(write_dir, "WRITE_SIZE")
+    Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    half = Vh * 12 * Ns * 16
+    cal_f = [v for nm, v in f if "k_site<16, false, double>" in nm]
+    cal_w = [v for nm, v in w if "k_site<16, false, double>" in nm]
+    ff = half / (sum(cal_f) / len(cal_f) * 1024)
+    wf = half / (sum(cal_w) / len(cal_w) * 1024)
+    alg = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)
+    res = {"kernel": "FP64 fused hop with the A_T^-1 epilogue (k_hop / k_hop_tw <16, false, HM_SITE, false, double>)",
+           "lattice": "x".join(map(str, dims)), "Ns": Ns, "commands": [fetch_cmd, write_cmd],
+           "calibration": {"kernel": f"k_site<16, false, double> (reads and writes one FP64 half field, {half} bytes "
+                                     "each way)", "fetch_kib": cal_f, "write_kib": cal_w,
+                           "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "algorithmic_bytes_per_launch": alg, "by_schedule": {}, "source_sha1": source_sha1(),
+           "source_files": KERNEL_SOURCES}
+
+    def hops(rows):
+        return [v for nm, v in rows if re.search(r"k_hop(_tw)?<16, false, 1, false, double", nm)]
+    hf, hw = hops(f), hops(w)
+    # profile_hop.py: per schedule, 2 untimed + nrep timed launches; keep the nrep timed ones
+    per = nrep + 2
+    for i, s in enumerate(scheds):
+        fk = hf[i * per + 2:(i + 1) * per]
+        wk = hw[i * per + 2:(i + 1) * per]
+        rd = ff * 1024 * sum(fk) / len(fk)
+        wr = wf * 1024 * sum(wk) / len(wk)
+        res["by_schedule"][s] = {"kernel": "k_hop_tw" if s.startswith(("3,", "5,")) else "k_hop",
+                                 "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
+                                 "read_bytes_per_launch": round(rd), "write_bytes_per_launch": round(wr),
+                                 "bytes_per_launch": round(rd + wr), "amplification": round((rd + wr) / alg, 4)}
+    with open(out_json, "w") as fo:
+        json.dump(res, fo, indent=1)
+    print(out_json, {k: v["amplification"] for k, v in res["by_schedule"].items()})
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace(*sys.argv[2:6])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:7])
+    else:
+        raise SystemExit(__doc__)
