@@ -179,6 +179,38 @@ eofa_status eofa_solve_ht(eofa_ctx *ctx, double m_plus, double m_minus, const vo
 eofa_status eofa_apply_static(eofa_ctx *ctx, int op, double m_plus, double m_minus, const void *in, void *out,
                               eofa_precision prec);
 
+/*
+ * Heat-bath pseudofermions (Sec. I, Eq.(CG_gaussian)): the field phi with weight exp(-S), S = phi^dag A phi for a
+ * chiral action A (as in eofa_chiral_action, out = A phi), drawn from Gaussian noise eta of weight
+ * exp(-eta^dag eta) as phi = A^{-1/2} P_c eta.  x^{-1/2} is replaced by Zolotarev's optimal rational
+ * approximation on [lo, hi] with the fewest poles (<= 8) whose relative error is <= rel_err; each pole's term
+ * (A + b)^{-1} P_c eta equals a chiral action at a shifted mass (between the action's two masses m_a < m_b) over
+ * (1 + b), and all of them are solved together through the multi-RHS path under params.  lo = hi = 0 takes
+ * [0.9 r, 1.1 / r], r = (1 + m_a) / (1 + m_b), which holds the spectrum on the measured fields (it is [r, 1]
+ * there); a spectrum outside [lo, hi] shows in info.check.  eta, phi: 4D canonical device buffers (no alias);
+ * phi's other chiral half is set to zero.
+ */
+typedef struct {
+    int npoles;                /* poles of the rational approximation (0 when the action is the identity) */
+    double approx_err;         /* its max relative error on [lo, hi] */
+    double lo, hi;             /* the interval used */
+    double check;              /* verify != 0: phi^dag A phi / |P_c eta|^2 - 1 (one more solve); else 0 */
+    int iters_max;             /* largest iteration count of the shifted solves */
+    double true_rel_resid_max; /* largest true residual of the shifted solves */
+    double seconds;
+} eofa_heatbath_info;
+eofa_status eofa_chiral_heatbath(eofa_ctx *ctx, int chir, double m3, double m4, double mo, const void *eta,
+                                 void *phi, double lo, double hi, double rel_err, int verify,
+                                 const eofa_solve_params *params, eofa_heatbath_info *info);
+/* phi with weight exp(-phi^dag H^{-1}(m_hi, m_lo) phi) (Eq.(Hij)): the - action (m_lo,m_lo)/(m_lo,m_hi) on the
+ * P_- half of eta and the + action (m_lo,m_hi)/(m_hi,m_hi) on the P_+ half, default intervals; info[2] may be
+ * NULL. */
+eofa_status eofa_heatbath(eofa_ctx *ctx, double m_lo, double m_hi, const void *eta, void *phi, double rel_err,
+                          int verify, const eofa_solve_params *params, eofa_heatbath_info info[2]);
+/* The rational approximation above without a context (host only): x^{-1/2} ~ a0 + sum_{l < n} a[l] / (x + b[l])
+ * on [lo, hi] with n <= 8 poles; *err = its max relative error on [lo, hi]. */
+eofa_status eofa_inv_sqrt_rational(double lo, double hi, int n, double *a0, double *a, double *b, double *err);
+
 /* n systems H_T(m_plus[j], m_minus[j]) x5[j] = b5[j] solved together (the multi-RHS form of eofa_solve_ht; host
  * arrays of n device pointers to 5D canonical buffers, b5[j] != x5[j]).  Up to 8 systems share each launch
  * sequence, as in eofa_chiral_action_batch; info[j] per system (may be NULL). */

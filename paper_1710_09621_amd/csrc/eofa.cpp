@@ -82,6 +82,8 @@ struct eofa_ctx {
     double* partials_mr = nullptr;
     int pstride = 0;
     std::map<std::tuple<int, double, double>, SiteOp*> tabs;
+    void* hb = nullptr;  // heat-bath: the 4D outputs of the shifted chiral actions
+    size_t hb_bytes = 0;
     std::string err;
     // device time of the FP64 CG iteration's kernels (eofa_kernel_timing): HIP events around each launch
     bool timing = false;
@@ -1360,6 +1362,188 @@ eofa_status solve_ht_impl(eofa_ctx* ctx, double mp, double mm, const void* b5, v
     return EOFA_OK;
 }
 
+// ------------------------------------------------------------------ heat-bath (Sec. I, Eq.(CG_gaussian))
+// The pseudofermion of a chiral action S = phi^dag A phi is drawn as phi = A^{-1/2} P_c eta from Gaussian noise
+// eta.  x^{-1/2} is replaced on the interval [lo, hi] that holds the spectrum of A by Zolotarev's optimal
+// rational function in partial fractions, a0 + sum_l a_l / (x + b_l) (b_l > 0), so
+//     phi = a0 P_c eta + sum_l a_l (A + b_l)^{-1} P_c eta.
+// For the - action A = 1 - k Om^T H_T(m3, m4)^{-1} Om P_-, the Woodbury identity and the rank-one mass
+// difference H_T(m3, m4') = H_T(m3, m4) - k(m4', m4) P_- Om Om^T give
+//     (1 + b) (A + b)^{-1} eta = P_- [eta + c Om^T H_T(m3, m4')^{-1} Om P_- eta],  k(m4', m4) = c = k / (1 + b),
+// which is the - chiral action (m3, m4') / (m3, m4) of eta; likewise the + action with m3' from
+// k(m3', m3) = k / (1 + b) and the other mass m3.  The shifted masses lie between the action's two masses, and
+// every pole's system goes through one multi-RHS launch sequence.
+
+// complete elliptic integral of the first kind K(k) (modulus k < 1) by the arithmetic-geometric mean
+double ellip_K(double k) {
+    double a = 1.0, b = std::sqrt((1.0 - k) * (1.0 + k));
+    for (int i = 0; i < 64 && std::fabs(a - b) > 1e-16 * a; i++) {
+        const double an = 0.5 * (a + b);
+        b = std::sqrt(a * b);
+        a = an;
+    }
+    return M_PI / (2.0 * a);
+}
+
+// Jacobi elliptic sn(u, k) and cn(u, k) by the descending Landen (AGM) scheme
+void ellip_sncn(double u, double k, double& sn, double& cn) {
+    double a[64], c[64];
+    double b = std::sqrt((1.0 - k) * (1.0 + k));
+    a[0] = 1.0;
+    c[0] = k;
+    int n = 0;
+    while (n < 62 && std::fabs(c[n]) > 1e-17) {
+        a[n + 1] = 0.5 * (a[n] + b);
+        c[n + 1] = 0.5 * (a[n] - b);
+        b = std::sqrt(a[n] * b);
+        n++;
+    }
+    double phi = std::ldexp(1.0, n) * a[n] * u;
+    for (int i = n; i > 0; i--) phi = 0.5 * (phi + std::asin(c[i] * std::sin(phi) / a[i]));
+    sn = std::sin(phi);
+    cn = std::cos(phi);
+}
+
+struct RatInvSqrt {
+    int n = 0;
+    double a0 = 1.0, a[HB_MAXTERMS] = {}, b[HB_MAXTERMS] = {};
+    double err = 0.0;  // max |sqrt(x) r(x) - 1| on [lo, hi] (dense geometric grid)
+};
+
+// Zolotarev's optimal relative approximation of x^{-1/2} on [lo, hi] with n poles: zeros and poles
+// c_j = lo sn^2 / cn^2 (j K' / (2n + 1); k'), k' = sqrt(1 - lo / hi), K' = K(k'), poles at -c_{2l-1} and zeros
+// at -c_{2l}; the overall factor makes sqrt(x) r(x) equioscillate about 1.
+RatInvSqrt zolotarev_inv_sqrt(double lo, double hi, int n) {
+    RatInvSqrt r;
+    r.n = n;
+    const double kp = std::sqrt(1.0 - lo / hi), K = ellip_K(kp);
+    std::vector<double> c(2 * n + 1);
+    for (int j = 1; j <= 2 * n; j++) {
+        double sn, cn;
+        ellip_sncn(j * K / (2 * n + 1), kp, sn, cn);
+        c[j] = lo * sn * sn / (cn * cn);
+    }
+    double R[HB_MAXTERMS];
+    for (int l = 0; l < n; l++) {  // residue of prod (x + z_j) / (x + p_j) at the pole -p_l
+        const double pl = c[2 * l + 1];
+        double num = 1.0, den = 1.0;
+        for (int j = 0; j < n; j++) {
+            num *= c[2 * j + 2] - pl;
+            if (j != l) den *= c[2 * j + 1] - pl;
+        }
+        R[l] = num / den;
+        r.b[l] = pl;
+    }
+    auto e = [&](double x) {
+        double v = 1.0;
+        for (int l = 0; l < n; l++) v += R[l] / (x + r.b[l]);
+        return std::sqrt(x) * v;
+    };
+    const int G = 8001;
+    double emax = 0, emin = 1e300;
+    for (int i = 0; i < G; i++) {
+        const double v = e(lo * std::pow(hi / lo, (double)i / (G - 1)));
+        emax = std::max(emax, v);
+        emin = std::min(emin, v);
+    }
+    const double D = 2.0 / (emax + emin);
+    r.a0 = D;
+    for (int l = 0; l < n; l++) r.a[l] = D * R[l];
+    r.err = std::max(D * emax - 1.0, 1.0 - D * emin);
+    return r;
+}
+
+// the fewest poles (<= HB_MAXTERMS) whose error on [lo, hi] is at most rel_err
+RatInvSqrt choose_inv_sqrt(eofa_ctx* ctx, double lo, double hi, double rel_err) {
+    RatInvSqrt r;
+    for (int n = 1; n <= HB_MAXTERMS; n++) {
+        r = zolotarev_inv_sqrt(lo, hi, n);
+        if (r.err <= rel_err) return r;
+    }
+    REQUIRE(false, EOFA_EINVAL, "heat-bath: rel_err " + std::to_string(rel_err) + " needs more than " +
+                                    std::to_string(HB_MAXTERMS) + " poles on [lo, hi]");
+    return r;
+}
+
+// the mass m' with k(m', m) = c (between m and the mass whose k it divides)
+double shifted_mass(double m, double c) { return (2.0 * m + c * (1.0 + m)) / (2.0 - c * (1.0 + m)); }
+
+// phi (+)= A^{-1/2} P_chir eta for the chiral action (chir, m3, m4, mo)
+eofa_status heatbath_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* eta, void* phi,
+                          double lo, double hi, double rel_err, const eofa_solve_params* P, int accumulate,
+                          int verify, eofa_heatbath_info* info) {
+    check_params(ctx, P);
+    check_action(ctx, chir, m3, m4, mo, eta, phi);
+    REQUIRE(rel_err > 0 && rel_err < 1, EOFA_EINVAL, "rel_err must lie in (0, 1)");
+    auto t0 = std::chrono::steady_clock::now();
+    const double ma = std::min(chir < 0 ? m4 : m3, mo), mb = std::max(chir < 0 ? m4 : m3, mo);
+    const double rr = (1.0 + ma) / (1.0 + mb);
+    if (lo <= 0 && hi <= 0) { lo = 0.9 * rr; hi = 1.1 / rr; }
+    REQUIRE(lo > 0 && hi > lo, EOFA_EINVAL, "heat-bath: need 0 < lo < hi (or both 0 for the default)");
+    const double k = action_k(chir, m3, m4, mo);
+    RatInvSqrt R;
+    if (k != 0.0) R = choose_inv_sqrt(ctx, lo, hi, rel_err);  // k = 0: A = 1, phi = P_c eta exactly
+    const size_t n4 = (size_t)ctx->g.Vh * 2 * 12;            // complex elements of a 4D field
+    const size_t need = (size_t)(R.n + 1) * n4 * sizeof(cd);
+    if (ctx->hb_bytes < need) {
+        if (ctx->hb) HIPCHK(hipFree(ctx->hb));
+        ctx->hb = nullptr;
+        ctx->hb_bytes = 0;
+        HIPCHK(hipMalloc(&ctx->hb, need));
+        ctx->hb_bytes = need;
+    }
+    std::vector<int> ch(R.n, chir);
+    std::vector<double> a3(R.n), a4(R.n), ao(R.n), Sj(R.n);
+    std::vector<const void*> src(R.n, eta);
+    std::vector<void*> dst(R.n);
+    std::vector<eofa_solve_info> inf(R.n);
+    HbTerms t{};
+    t.a0 = R.a0;
+    t.n = R.n;
+    for (int l = 0; l < R.n; l++) {
+        const double c = k / (1.0 + R.b[l]);
+        if (chir < 0) { a3[l] = m3; a4[l] = shifted_mass(m4, c); ao[l] = m4; }
+        else { a3[l] = shifted_mass(m3, c); a4[l] = m4; ao[l] = m3; }
+        dst[l] = (void*)((cd*)ctx->hb + (size_t)l * n4);
+        t.out[l] = (const cd*)dst[l];
+        t.coef[l] = R.a[l] / (1.0 + R.b[l]);
+    }
+    eofa_status st = EOFA_OK;
+    if (R.n > 0) {
+        st = chiral_batch_impl(ctx, R.n, ch.data(), a3.data(), a4.data(), ao.data(), src.data(), dst.data(), nullptr,
+                               Sj.data(), P, inf.data());
+        if (st != EOFA_OK && st != EOFA_ENOCONV) return st;
+    }
+    HIPCHK(launch_hb_combine((const cd*)eta, (cd*)phi, t, n4, chir, accumulate, red_of(ctx, SC_TMP + 16, EPI_STORE),
+                             ctx->st));
+    sync_scal(ctx);
+    const double eta2 = ctx->hscal[SC_TMP + 16];
+    double check = 0.0;
+    if (verify) {  // S(phi) = phi^dag A phi (the action reads the P_c half of phi only) against |P_c eta|^2
+        double S = 0;
+        eofa_solve_info vi{};
+        const eofa_status s2 = chiral_impl(ctx, chir, m3, m4, mo, phi, (void*)((cd*)ctx->hb + (size_t)R.n * n4), 0, &S,
+                                           P, &vi);
+        if (s2 != EOFA_OK && s2 != EOFA_ENOCONV) return s2;
+        check = eta2 > 0 ? S / eta2 - 1.0 : 0.0;
+    }
+    if (info) {
+        info->npoles = R.n;
+        info->approx_err = R.err;
+        info->lo = lo;
+        info->hi = hi;
+        info->check = check;
+        info->iters_max = 0;
+        info->true_rel_resid_max = 0;
+        for (const auto& i : inf) {
+            info->iters_max = std::max(info->iters_max, i.iters);
+            info->true_rel_resid_max = std::max(info->true_rel_resid_max, i.true_rel_resid);
+        }
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
 // nrep launches of the fused hop (A_T^{-1} epilogue) alternating parities on workspace buffers,
 // under schedule sc; returns the average device ms per launch.
 double time_hop(eofa_ctx* ctx, int prec, int nrep, const Sched& sc) {
@@ -1817,6 +2001,36 @@ eofa_status eofa_apply_static(eofa_ctx* ctx, int op, double m_plus, double m_min
     });
 }
 
+eofa_status eofa_chiral_heatbath(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* eta, void* phi,
+                                 double lo, double hi, double rel_err, int verify, const eofa_solve_params* params,
+                                 eofa_heatbath_info* info) {
+    return guarded(ctx, [&]() {
+        return heatbath_impl(ctx, chir, m3, m4, mo, eta, phi, lo, hi, rel_err, params, 0, verify, info);
+    });
+}
+
+eofa_status eofa_heatbath(eofa_ctx* ctx, double m_lo, double m_hi, const void* eta, void* phi, double rel_err,
+                          int verify, const eofa_solve_params* params, eofa_heatbath_info info[2]) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(m_lo > 0 && m_lo <= m_hi && m_hi <= 1, EOFA_EINVAL, "need 0 < m_lo <= m_hi <= 1");
+        eofa_status a = heatbath_impl(ctx, -1, m_lo, m_lo, m_hi, eta, phi, 0, 0, rel_err, params, 0, verify,
+                                      info ? &info[0] : nullptr);
+        if (a != EOFA_OK && a != EOFA_ENOCONV) return a;
+        eofa_status b = heatbath_impl(ctx, +1, m_lo, m_hi, m_hi, eta, phi, 0, 0, rel_err, params, 1, verify,
+                                      info ? &info[1] : nullptr);
+        return b != EOFA_OK ? b : a;
+    });
+}
+
+eofa_status eofa_inv_sqrt_rational(double lo, double hi, int n, double* a0, double* a, double* b, double* err) {
+    if (!(lo > 0 && hi > lo) || n < 1 || n > HB_MAXTERMS || !a0 || !a || !b) return EOFA_EINVAL;
+    const RatInvSqrt r = zolotarev_inv_sqrt(lo, hi, n);
+    *a0 = r.a0;
+    for (int l = 0; l < n; l++) { a[l] = r.a[l]; b[l] = r.b[l]; }
+    if (err) *err = r.err;
+    return EOFA_OK;
+}
+
 eofa_status eofa_graph_stats(eofa_ctx* ctx, long* replays, int* cached) {
     return guarded(ctx, [&]() -> eofa_status {
         if (replays) *replays = ctx->graph_replays;
@@ -2119,6 +2333,7 @@ void eofa_destroy(eofa_ctx* ctx) {
     }
     if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
     if (ctx->partials) (void)hipFree(ctx->partials);
+    if (ctx->hb) (void)hipFree(ctx->hb);
     if (ctx->partials_mr) (void)hipFree(ctx->partials_mr);
     {
         auto& c = ctx->cnn;

@@ -101,6 +101,17 @@ hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, 
 hipError_t launch_finish(const Red& r, unsigned nblocks, hipStream_t st);
 // dst[i] = host_vals[i], i < n <= 64 (values travel as kernel arguments: the host array may die at once)
 hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream_t st);
+// Terms of the heat-bath combination phi = a0 P_chir eta + sum_l coef[l] out[l] (canonical 4D fields).
+constexpr int HB_MAXTERMS = 8;
+struct HbTerms {
+    const cd* out[HB_MAXTERMS];
+    double coef[HB_MAXTERMS];
+    double a0;
+    int n;
+};
+// the combination over the n complex elements of a 4D field; |P_chir eta|^2 goes through red
+hipError_t launch_hb_combine(const cd* eta, cd* phi, const HbTerms& t, size_t n, int chir, int accumulate,
+                             const Red& red, hipStream_t st);
 // dst[i] = host_vals[i] for any n, in chunks of 64 values travelling as kernel arguments
 hipError_t launch_set_block(double* dst, size_t n, const double* host_vals, hipStream_t st);
 // bytes (a multiple of 8) of dst set to zero / copied from src, by kernels

@@ -952,6 +952,29 @@ __global__ __launch_bounds__(256) void k_copy(double* __restrict__ dst, const do
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) dst[i] = src[i];
 }
 
+// Heat-bath combination: phi = a0 P_chir eta + sum_l coef[l] out[l] (+ phi when accumulate) at every site, with
+// the partial sums of |P_chir eta|^2.  One thread per (site, component) of the canonical 4D field.
+__global__ __launch_bounds__(256) void k_hb_combine(const cd* __restrict__ eta, cd* __restrict__ phi, const HbTerms t,
+                                                    size_t n, int chir, int accumulate, Red red) {
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const int spin = (int)((i % 12) / 3);
+        const bool keep = (chir > 0) ? (spin < 2) : (spin >= 2);
+        const cd e = eta[i];
+        cd v = keep ? cd{t.a0 * e.x, t.a0 * e.y} : cd{0.0, 0.0};
+        for (int l = 0; l < t.n; l++) {
+            const cd o = t.out[l][i];
+            v.x = fma(t.coef[l], o.x, v.x);
+            v.y = fma(t.coef[l], o.y, v.y);
+        }
+        if (accumulate) { const cd p = phi[i]; v.x += p.x; v.y += p.y; }
+        phi[i] = v;
+        if (keep) acc += e.x * e.x + e.y * e.y;
+    }
+    __shared__ double lds[4];
+    finish_sum(red, block_sum256(acc, lds));
+}
+
 struct Vec64 {
     double v[64];
 };
@@ -1210,6 +1233,14 @@ hipError_t launch_set_vec(double* dst, int n, const double* host_vals, hipStream
     Vec64 v{};
     for (int i = 0; i < n; i++) v.v[i] = host_vals[i];
     hipLaunchKernelGGL(k_set_vec, dim3(1), dim3(64), 0, st, dst, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_hb_combine(const cd* eta, cd* phi, const HbTerms& t, size_t n, int chir, int accumulate,
+                             const Red& red, hipStream_t st) {
+    if (t.n < 0 || t.n > HB_MAXTERMS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_hb_combine, dim3(nblk(n)), dim3(256), 0, st, eta, phi, t, n, chir, accumulate, red);
+    finish(red, (unsigned)nblk(n), st);
     return hipGetLastError();
 }
 

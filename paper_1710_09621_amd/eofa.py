@@ -23,6 +23,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, ESTATE, ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
 PC_NONE, PC_LEARNED = 0, 1
 CNN_NPARAM = 4 * (81 * 32 * 32 + 32)
+HB_BATCH = 8  # the heat-bath's shifted solves run as one multi-RHS batch of at most 8 systems
 OPS = dict(DW=0, HOP=1, DT=2, DT_DAG=3, HT=4, AT_INV=5, SCHUR=6, SCHUR_DAG=7, SCHUR_NORMAL=8)
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "ESTATE", -6: "ENOTIMPL"}
 
@@ -44,6 +45,15 @@ KERNELS = ("hop", "schur_w", "hop_dag", "schur_q", "xp")  # K1 .. K5 of one FP64
 
 class KernelStats(C.Structure):
     _fields_ = [("ms", C.c_double * NKERN), ("launches", C.c_long * NKERN), ("bytes", C.c_double * NKERN)]
+
+
+class HeatbathInfo(C.Structure):
+    _fields_ = [("npoles", C.c_int), ("approx_err", C.c_double), ("lo", C.c_double), ("hi", C.c_double),
+                ("check", C.c_double), ("iters_max", C.c_int), ("true_rel_resid_max", C.c_double),
+                ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class SolveInfo(C.Structure):
@@ -84,6 +94,10 @@ def load():
         "eofa_hinv_batch": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double), PP, PP, C.POINTER(C.c_double),
                             C.POINTER(SolveParams), C.POINTER(SolveInfo)],
         "eofa_solve_ht": [P, D, D, P, P, C.POINTER(SolveParams), C.POINTER(SolveInfo)],
+        "eofa_chiral_heatbath": [P, I, D, D, D, P, P, D, D, D, I, C.POINTER(SolveParams), C.POINTER(HeatbathInfo)],
+        "eofa_heatbath": [P, D, D, P, P, D, I, C.POINTER(SolveParams), C.POINTER(HeatbathInfo)],
+        "eofa_inv_sqrt_rational": [D, D, I, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)],
         "eofa_solve_ht_batch": [P, I, C.POINTER(C.c_double), C.POINTER(C.c_double), PP, PP, C.POINTER(SolveParams),
                                 C.POINTER(SolveInfo)],
         "eofa_apply": [P, I, D, D, P, P, I],
@@ -117,11 +131,24 @@ def exported_symbols():
     """Names the library exports (for the ABI test)."""
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
-                        "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht", "eofa_solve_ht_batch",
+                        "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht", "eofa_solve_ht_batch", "eofa_chiral_heatbath", "eofa_heatbath",
+                        "eofa_inv_sqrt_rational",
                         "eofa_apply", "eofa_apply_static", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
                         "eofa_kernel_timing", "eofa_cg_block", "eofa_graph_stats", "eofa_set_precond",
                         "eofa_last_error", "eofa_destroy") if hasattr(lib, n)]
+
+
+def inv_sqrt_rational(lo, hi, n):
+    """The heat-bath's rational approximation of x^{-1/2} on [lo, hi] with n poles (host only):
+    (a0, a[n], b[n], err) with x^{-1/2} ~ a0 + sum a_l / (x + b_l)."""
+    lib = load()
+    a0, err = C.c_double(), C.c_double()
+    a, b = (C.c_double * n)(), (C.c_double * n)()
+    st = lib.eofa_inv_sqrt_rational(float(lo), float(hi), int(n), C.byref(a0), a, b, C.byref(err))
+    if st != OK:
+        raise EofaError(st, "eofa_inv_sqrt_rational")
+    return a0.value, np.array(a[:]), np.array(b[:]), err.value
 
 
 def _ptr(t):
@@ -245,6 +272,31 @@ class Context:
         st = self.lib.eofa_solve_ht_batch(self.h, n, mp, mm, pb, px, C.byref(p), info)
         self._check(st, "solve_ht_batch")
         return [(xs[j], info[j].as_dict()) for j in range(n)]
+
+    def chiral_heatbath(self, chir, m3, m4, mo, eta, rel_err=1e-12, lo=0.0, hi=0.0, verify=False, p=None):
+        """phi = A^{-1/2} P_c eta for the chiral action A (chir, m3, m4, mo); returns (phi, info)."""
+        p = p or params()
+        eta = self._c128(eta, self.shape4)
+        phi = self.torch.empty_like(eta)
+        self._prep_ws(p, HB_BATCH)
+        info = HeatbathInfo()
+        st = self.lib.eofa_chiral_heatbath(self.h, int(chir), float(m3), float(m4), float(mo), _ptr(eta), _ptr(phi),
+                                           float(lo), float(hi), float(rel_err), int(bool(verify)), C.byref(p),
+                                           C.byref(info))
+        self._check(st, "chiral_heatbath")
+        return phi, info.as_dict()
+
+    def heatbath(self, eta, m_lo, m_hi, rel_err=1e-12, verify=False, p=None):
+        """phi with weight exp(-phi^dag H^{-1}(m_hi, m_lo) phi); returns (phi, [info_minus, info_plus])."""
+        p = p or params()
+        eta = self._c128(eta, self.shape4)
+        phi = self.torch.empty_like(eta)
+        self._prep_ws(p, HB_BATCH)
+        info = (HeatbathInfo * 2)()
+        st = self.lib.eofa_heatbath(self.h, float(m_lo), float(m_hi), _ptr(eta), _ptr(phi), float(rel_err),
+                                    int(bool(verify)), C.byref(p), info)
+        self._check(st, "heatbath")
+        return phi, [i.as_dict() for i in info]
 
     def set_workspace(self, buf):
         """Hand the library a caller-owned device buffer (a torch tensor, kept alive here) as its workspace."""
