@@ -209,7 +209,10 @@ def main():
     traffic = measured_traffic(args.traffic, dims, Ns, sched64)
     kern = {3: "k_hop_tw<16, false, HM_SITE, false, double, false> (u = A_T^{-1} H_eo p; t-walk schedule)",
             5: "k_hop_tw<16, false, HM_SITE, false, double, true> (u = A_T^{-1} H_eo p; t-walk schedule, x "
-               "neighbours from LDS)"}.get(sched64[0], "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)")
+               "neighbours from LDS)",
+            6: "k_hop_tws<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p; t-walk schedule, x neighbours "
+               "from LDS, two lanes per site and slice)"}.get(sched64[0],
+                                                             "k_hop<16, false, HM_SITE, false, double> (u = A_T^{-1} H_eo p)")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -1632,10 +1632,10 @@ std::vector<Sched> sched_candidates(const eofa_ctx* ctx, int prec) {
             for (int tz : opts)
                 for (int tt : {16, g.Lt})
                     for (int pad : {0, 48})
-                        for (int mode : {3, 5}) {
-                            // mode 5 already holds the whole LDS of a CU (one workgroup per CU): a reserve would be
-                            // clamped to nothing and only duplicate the candidate
-                            if (mode == 5 && pad) continue;
+                        for (int mode : {3, 5, 6}) {
+                            // modes 5 and 6 already hold the whole LDS of a CU (one workgroup per CU): a reserve
+                            // would be clamped to nothing and only duplicate the candidate
+                            if (mode >= 5 && pad) continue;
                             const Sched s{mode, 1, ty, tz, tt, nyb, pad};
                             const int per = ty * tz;
                             if (per < 8 || per > 64 || tw_grid(g, ctx->Ns, s) == 0) continue;

@@ -135,31 +135,33 @@ __device__ __forceinline__ void siteop_store(SiteOpL<NS>& d, const SiteOpShare<N
     }
 }
 
-template <int NS, int SIG, int K, typename R, typename T>
-__device__ __forceinline__ void ring_scan_step(cpx<R> v[6], const T& t, int s, int lane) {
+// NC: the number of colour-spin components of the chirality half held by this lane (6, or 3 when the two
+// spins of a half sit in two lanes); every component is transformed independently.
+template <int NS, int SIG, int K, int NC = 6, typename R, typename T>
+__device__ __forceinline__ void ring_scan_step(cpx<R> v[NC], const T& t, int s, int lane) {
     if constexpr (K < ilog2(NS)) {
         const R qk = (R)t.q[K][s];
         constexpr int OFF = SIG * (1 << K);
 #pragma unroll
-        for (int j = 0; j < 6; j++) {
+        for (int j = 0; j < NC; j++) {
             cpx<R> o = lane_from_c<NS, OFF>(v[j], lane);
             v[j].x = fma(qk, o.x, v[j].x);
             v[j].y = fma(qk, o.y, v[j].y);
         }
-        ring_scan_step<NS, SIG, K + 1>(v, t, s, lane);
+        ring_scan_step<NS, SIG, K + 1, NC>(v, t, s, lane);
     }
 }
 
 // ORDER 0: solve then shift (A^{-1}-type ops).  ORDER 1: shift then solve (their transposes).
-template <int NS, int SIG, int ORDER, typename R, typename T>
-__device__ __forceinline__ void chir_op(cpx<R> v[6], const T& t, int s, int lane) {
+template <int NS, int SIG, int ORDER, int NC = 6, typename R, typename T>
+__device__ __forceinline__ void chir_op(cpx<R> v[NC], const T& t, int s, int lane) {
     const R pre = (R)t.pre[s], post = (R)t.post[s], shf = (R)t.shf[s];
 #pragma unroll
-    for (int j = 0; j < 6; j++) v[j] = cscale(pre, v[j]);
+    for (int j = 0; j < NC; j++) v[j] = cscale(pre, v[j]);
     if constexpr (ORDER == 0) {
-        ring_scan_step<NS, SIG, 0>(v, t, s, lane);
+        ring_scan_step<NS, SIG, 0, NC>(v, t, s, lane);
 #pragma unroll
-        for (int j = 0; j < 6; j++) {
+        for (int j = 0; j < NC; j++) {
             cpx<R> o = lane_from_c<NS, SIG>(v[j], lane);
             v[j].x = post * fma(shf, o.x, v[j].x);
             v[j].y = post * fma(shf, o.y, v[j].y);
@@ -167,14 +169,14 @@ __device__ __forceinline__ void chir_op(cpx<R> v[6], const T& t, int s, int lane
     } else {
         const R mid = (R)t.mid[s];
 #pragma unroll
-        for (int j = 0; j < 6; j++) {
+        for (int j = 0; j < NC; j++) {
             cpx<R> o = lane_from_c<NS, SIG>(v[j], lane);
             v[j].x = mid * fma(shf, o.x, v[j].x);
             v[j].y = mid * fma(shf, o.y, v[j].y);
         }
-        ring_scan_step<NS, SIG, 0>(v, t, s, lane);
+        ring_scan_step<NS, SIG, 0, NC>(v, t, s, lane);
 #pragma unroll
-        for (int j = 0; j < 6; j++) v[j] = cscale(post, v[j]);
+        for (int j = 0; j < NC; j++) v[j] = cscale(post, v[j]);
     }
 }
 
@@ -186,6 +188,16 @@ __device__ __forceinline__ void site_op(cpx<R> v[12], const Op& op, int s, int l
     constexpr int ORD = DAG ? 1 : 0;
     chir_op<NS, SU, ORD>(v, op.h[0], s, lane);
     chir_op<NS, -SU, ORD>(v + 6, op.h[1], s, lane);
+}
+
+// The same operator on one upper spin v[0..2] and one lower spin v[3..5] (3 colours each): the share of a lane
+// of the spin-split hop, whose partner lane holds the other spin of each half.
+template <int NS, bool DAG, typename R, typename Op>
+__device__ __forceinline__ void site_op_half(cpx<R> v[6], const Op& op, int s, int lane) {
+    constexpr int SU = DAG ? +1 : -1;
+    constexpr int ORD = DAG ? 1 : 0;
+    chir_op<NS, SU, ORD, 3>(v, op.h[0], s, lane);
+    chir_op<NS, -SU, ORD, 3>(v + 3, op.h[1], s, lane);
 }
 
 // ------------------------------------------------------------------ spin projection (chiral basis)

@@ -486,6 +486,345 @@ __global__ __launch_bounds__(256, 1) void k_hop_tw(const HopArgs<R> a) {
     }
 }
 
+// ===================================================================== spin-split t-walk form of the hop
+// (Sched mode 6.)  The t-walk over whole x-lines with the x neighbours from LDS (mode 5), with two lanes per
+// (site, s): the lanes of half H (waves 0-3 for H = 0, waves 4-7 for H = 1 of a 512-lane workgroup) form the
+// H-th spin component of every projected half-spinor.  For direction mu that component reads the upper spin
+// H and one lower spin of the neighbour column and adds into the same two spins of the output: the lower spin
+// 1 - H for x and y, H for z and t.  A lane therefore accumulates the upper spin H throughout, the lower spin
+// 1 - H over x and y, and the lower spin H over z and t; between y and z the halves swap their lower-spin
+// partial sums through LDS, so every output component collects its eight terms in the order of the unsplit
+// hop and the operator is bitwise that of k_hop.  A lane holds half of each column, which leaves registers
+// for two waves per SIMD on the same working set of lattice lines as mode 5.
+
+// lower spin that component H of direction MU reads and writes
+template <int MU, int H> constexpr int low_spin() { return MU < 2 ? 1 - H : H; }
+
+// h = component H of the projection (1 + S gamma_MU) psi from the upper spin H (up) and the lower spin
+// low_spin<MU, H> (dn) of psi; the same operations as project() on that component
+template <int MU, int S, int H, typename R>
+__device__ __forceinline__ void project_h(const cpx<R> up[3], const cpx<R> dn[3], cpx<R> h[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cpx<R> b;
+        if constexpr (MU == 0) b = cneg(ci(dn[c]));
+        else if constexpr (MU == 1) b = H == 0 ? cneg(dn[c]) : dn[c];
+        else if constexpr (MU == 2) b = H == 0 ? cneg(ci(dn[c])) : ci(dn[c]);
+        else b = dn[c];
+        h[c] = S > 0 ? cadd(up[c], b) : csub(up[c], b);
+    }
+}
+
+// adds component H of (1 + S gamma_MU)-reconstruction of w into the upper spin H (au) and the lower spin
+// low_spin<MU, H> (ad); the same operations as reconstruct() on that component
+template <int MU, int S, int H, typename R>
+__device__ __forceinline__ void reconstruct_h(cpx<R> au[3], cpx<R> ad[3], const cpx<R> w[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cpx<R> t;
+        if constexpr (MU == 0) t = ci(w[c]);
+        else if constexpr (MU == 1) t = H == 0 ? cneg(w[c]) : w[c];
+        else if constexpr (MU == 2) t = H == 0 ? ci(w[c]) : cneg(ci(w[c]));
+        else t = w[c];
+        au[c] = cadd(au[c], w[c]);
+        ad[c] = S > 0 ? cadd(ad[c], t) : csub(ad[c], t);
+    }
+}
+
+// w = U h or U^dag h for one spin component (the arithmetic of link_mul on that component)
+template <bool ADJ, typename R>
+__device__ __forceinline__ void link_mul3(const cpx<R>* U, const cpx<R> h[3], cpx<R> w[3]) {
+    cpx<R> u[9];
+#pragma unroll
+    for (int k = 0; k < 9; k++) u[k] = U[k];
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        cpx<R> a = {0, 0};
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            if constexpr (!ADJ) a = cmadd(a, u[3 * r + k], h[k]);
+            else a = cjmadd(a, u[3 * k + r], h[k]);
+        }
+        w[r] = a;
+    }
+}
+
+// the upper spin H and the lower spin L of column cb (12 NS complex per 4D site, s fastest)
+template <int NS, int H, int L, typename R>
+__device__ __forceinline__ void load_spins(cpx<R> up[3], cpx<R> dn[3], const cpx<R>* __restrict__ in, size_t cb, int s) {
+    const cpx<R>* col = in + cb * 12 * NS + s;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        up[c] = col[(3 * H + c) * NS];
+        dn[c] = col[(6 + 3 * L + c) * NS];
+    }
+}
+
+// one direction MU of component H from global memory: forward term at nb[2 MU], backward at nb[2 MU + 1]
+template <int NS, bool DAG, int MU, int H, typename R>
+__device__ __forceinline__ void hop_mu_h(cpx<R> au[3], cpx<R> ad[3], const cpx<R>* __restrict__ in, const cpx<R>* Uf,
+                                         const cpx<R>* Ub, const int nb[8], int s) {
+    constexpr int SF = DAG ? +1 : -1, SB = -SF, L = low_spin<MU, H>();
+    {
+        cpx<R> up[3], dn[3], h[3], w[3];
+        load_spins<NS, H, L>(up, dn, in, (size_t)nb[2 * MU], s);
+        project_h<MU, SF, H>(up, dn, h);
+        link_mul3<false>(Uf, h, w);
+        reconstruct_h<MU, SF, H>(au, ad, w);
+    }
+    {
+        cpx<R> up[3], dn[3], h[3], w[3];
+        load_spins<NS, H, L>(up, dn, in, (size_t)nb[2 * MU + 1], s);
+        project_h<MU, SB, H>(up, dn, h);
+        link_mul3<true>(Ub, h, w);
+        reconstruct_h<MU, SB, H>(au, ad, w);
+    }
+}
+
+// The links of the workgroup's sites staged in LDS by LPS lanes per site (lane li of site ls), slot 7 holding
+// U_t of the input site x + t (the t-walk's carry link); more_stores runs between the loads and the LDS writes.
+template <int LPS, typename R, typename F>
+__device__ __forceinline__ void stage_links_tw(cpx<R> (*sU)[8][9], const cpx<R>* __restrict__ Uown,
+                                               const cpx<R>* __restrict__ Uoth, int cb, const int nb[8], int ls, int li,
+                                               F more_stores) {
+    constexpr int NQ = (72 + LPS - 1) / LPS;
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 v[NQ];
+    const int n1 = nb[1], n3 = nb[3], n5 = nb[5], n6 = nb[6];
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        const int e = min(li + q * LPS, 71), l = e / 9, k = e % 9;
+        // the input site of backward link l as arithmetic on the four candidates (a select chain or an index
+        // into nb[] is turned into a private-memory table)
+        const int nbl = (l == 4) * n1 + (l == 5) * n3 + (l == 6) * n5 + (l == 7) * n6;
+        const cpx<R>* src = (l < 4) ? Uown + ((size_t)cb * 4 + l) * 9 + k : Uoth + ((size_t)nbl * 4 + (l - 4)) * 9 + k;
+        v[q] = *(const v2*)src;
+    }
+    more_stores();
+#pragma unroll
+    for (int q = 0; q < NQ; q++) {
+        const int e = li + q * LPS;
+        if (e < 72) *(v2*)&sU[ls][e / 9][e % 9] = v[q];
+    }
+    __syncthreads();
+}
+
+// Block-wide sum over 512 lanes (result valid in every thread).
+__device__ __forceinline__ double block_sum512(double v, double* lds8) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds8[w] = v;
+    __syncthreads();
+    return ((lds8[0] + lds8[1]) + (lds8[2] + lds8[3])) + ((lds8[4] + lds8[5]) + (lds8[6] + lds8[7]));
+}
+
+// The epilogue of MODE on this lane's share v (v[0..2] the upper spin H, v[3..5] the lower spin H) at (cb, s):
+// the operations of hop_epilogue on these components; returns this lane's part of the reduced norm.
+template <int NS, bool DAG, int MODE, bool RED, int H, typename R, typename TA, typename TB>
+__device__ __forceinline__ double hop_epilogue_h(const HopArgs<R>& a, cpx<R> z[6], int cb, int s, int lane,
+                                                 const TA& opA, const TB& opB) {
+    const size_t base = (size_t)cb * 12 * NS + s;
+    // offset of this lane's j-th component in a column: upper spin H (j < 3), then lower spin H
+#define J(j) ((((j) < 3) ? 3 * H + (j) : 3 + 3 * H + (j)) * NS)
+    double nrm = 0.0;
+    cpx<R> v[6];
+    if constexpr (MODE == HM_LIN || MODE == HM_SITE) {
+#pragma unroll
+        for (int j = 0; j < 6; j++) v[j] = cscale(a.cz, z[j]);
+        if (a.aux) {
+#pragma unroll
+            for (int j = 0; j < 6; j++) {
+                cpx<R> t = a.aux[base + J(j)];
+                v[j].x = fma(a.caux, t.x, v[j].x);
+                v[j].y = fma(a.caux, t.y, v[j].y);
+            }
+        }
+        if constexpr (MODE == HM_SITE) site_op_half<NS, DAG>(v, opA, s, lane);
+    } else if constexpr (MODE == HM_SCHUR_W) {
+        site_op_half<NS, false>(z, opA, s, lane);
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            cpx<R> t = a.aux[base + J(j)];
+            v[j].x = fma(a.cz, z[j].x, a.caux * t.x);
+            v[j].y = fma(a.cz, z[j].y, a.caux * t.y);
+        }
+    } else if constexpr (MODE == HM_SCHUR_Q) {
+        const R alpha = (R)a.scal[SC_ALPHA];
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            cpx<R> w = a.aux[base + J(j)], r = a.aux2[base + J(j)];
+            R qx = fma(a.cz, z[j].x, a.caux * w.x), qy = fma(a.cz, z[j].y, a.caux * w.y);
+            v[j].x = fma(-alpha, qx, r.x);
+            v[j].y = fma(-alpha, qy, r.y);
+        }
+    } else if constexpr (MODE == HM_DT || MODE == HM_DW) {
+        cpx<R> d[6], m[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) d[j] = a.self[base + J(j)];
+#pragma unroll
+        for (int j = 0; j < 6; j++) m[j] = d[j];
+        if constexpr (MODE == HM_DT) site_op_half<NS, DAG>(m, opA, s, lane);
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            R tx = a.diag * d[j].x - (R)0.5 * z[j].x, ty = a.diag * d[j].y - (R)0.5 * z[j].y;
+            if constexpr (MODE == HM_DT) { tx += m[j].x; ty += m[j].y; }
+            v[j] = {a.cz * tx, a.cz * ty};
+        }
+        if (a.aux) {
+#pragma unroll
+            for (int j = 0; j < 6; j++) {
+                cpx<R> t = a.aux[base + J(j)];
+                v[j].x = fma(a.caux, t.x, v[j].x);
+                v[j].y = fma(a.caux, t.y, v[j].y);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; j++) st_out(a.out + base + J(j), v[j]);
+    if constexpr (RED || MODE == HM_SCHUR_W) {
+#pragma unroll
+        for (int j = 0; j < 6; j++) nrm += (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+    }
+    if constexpr (MODE == HM_SCHUR_W) {
+        site_op_half<NS, true>(v, opB, s, lane);
+#pragma unroll
+        for (int j = 0; j < 6; j++) st_out(a.out2 + base + J(j), v[j]);
+    }
+    return nrm;
+#undef J
+}
+
+// backward t term of component H of the column of the input site cbi (U_t(cbi)^dag (1 + gamma_t) psi), kept
+// in this lane's carry slot (3 complex, stride 512)
+template <int NS, bool DAG, int H, typename R>
+__device__ __forceinline__ void tws_carry(cpx<R>* cw, const cpx<R>* __restrict__ in, const cpx<R>* __restrict__ Uoth,
+                                          int cbi, int s) {
+    constexpr int SB = DAG ? -1 : +1;
+    cpx<R> up[3], dn[3], h[3], w[3];
+    load_spins<NS, H, H>(up, dn, in, (size_t)cbi, s);
+    project_h<3, SB, H>(up, dn, h);
+    link_mul3<true>(Uoth + ((size_t)cbi * 4 + 3) * 9, h, w);
+#pragma unroll
+    for (int c = 0; c < 3; c++) cw[c * 512] = w[c];
+}
+
+// One t-walk step of component H at (cb, s): the operations of tw_step (XL form) on this lane's share.
+template <int NS, bool DAG, int MODE, bool RED, int H, typename R>
+__device__ __forceinline__ void tws_step(const HopArgs<R>& a, cpx<R> (*sU)[8][9], const SiteOpL<NS>& sA,
+                                         const SiteOpL<NS>& sB, int cb, int s, int lane, int ls, int q, cpx<R>* cw,
+                                         double& nrm, cpx<R> (*xl)[256], cpx<R> (*xch)[3][256]) {
+    constexpr int SF = DAG ? +1 : -1, SB = -SF;
+    HOP_FENCE();
+    int nb[8];
+    neighbours(a.g, cb, a.par, nb);
+    // the previous step's reads of sU end at the barrier between this step's link loads and LDS writes
+    stage_links_tw<2 * NS>(sU, a.Uown, a.Uoth, cb, nb, ls, H * NS + s, [] { __syncthreads(); });
+    cpx<R> au[3], ad[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) { au[c] = {0, 0}; ad[c] = {0, 0}; }
+    {   // x +- 1 are sites of this segment: site-lanes (ls + nb - cb) * NS + s of the LDS copy
+        constexpr int L = low_spin<0, H>();
+        const int lf = (ls + nb[0] - cb) * NS + s, lb = (ls + nb[1] - cb) * NS + s;
+        cpx<R> up[3], dn[3], h[3], w[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) { up[c] = xl[3 * H + c][lf]; dn[c] = xl[6 + 3 * L + c][lf]; }
+        project_h<0, SF, H>(up, dn, h);
+        link_mul3<false>(sU[ls][0], h, w);
+        reconstruct_h<0, SF, H>(au, ad, w);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { up[c] = xl[3 * H + c][lb]; dn[c] = xl[6 + 3 * L + c][lb]; }
+        project_h<0, SB, H>(up, dn, h);
+        link_mul3<true>(sU[ls][4], h, w);
+        reconstruct_h<0, SB, H>(au, ad, w);
+    }
+    HOP_FENCE();
+    hop_mu_h<NS, DAG, 1, H>(au, ad, a.in, sU[ls][1], sU[ls][5], nb, s);
+    HOP_FENCE();
+    // hand the x, y partial of the lower spin 1 - H to the other half and take its partial of the lower spin H;
+    // the barrier also ends every lane's reads of this step's x neighbours in xl
+#pragma unroll
+    for (int c = 0; c < 3; c++) xch[H][c][q] = ad[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; c++) ad[c] = xch[1 - H][c][q];
+    HOP_FENCE();
+    hop_mu_h<NS, DAG, 2, H>(au, ad, a.in, sU[ls][2], sU[ls][6], nb, s);
+    HOP_FENCE();
+    {
+        cpx<R> up[3], dn[3], h[3], w[3];
+        load_spins<NS, H, H>(up, dn, a.in, (size_t)nb[6], s);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { xl[3 * H + c][q] = up[c]; xl[6 + 3 * H + c][q] = dn[c]; }
+        project_h<3, SF, H>(up, dn, h);
+        link_mul3<false>(sU[ls][3], h, w);
+        reconstruct_h<3, SF, H>(au, ad, w);
+#pragma unroll
+        for (int c = 0; c < 3; c++) w[c] = cw[c * 512];
+        reconstruct_h<3, SB, H>(au, ad, w);  // backward t term, carried from two steps back
+        project_h<3, SB, H>(up, dn, h);
+        link_mul3<true>(sU[ls][7], h, w);    // the backward t term of slab t + 2
+#pragma unroll
+        for (int c = 0; c < 3; c++) cw[c * 512] = w[c];
+    }
+    HOP_FENCE();
+    cpx<R> z[6] = {au[0], au[1], au[2], ad[0], ad[1], ad[2]};
+    nrm += hop_epilogue_h<NS, DAG, MODE, RED, H>(a, z, cb, s, lane, sA, sB);
+    HOP_FENCE();
+}
+
+template <int NS, bool DAG, int MODE, bool RED, int H, typename R>
+__device__ __forceinline__ double tws_walk(const HopArgs<R>& a, cpx<R> (*sU)[8][9], const SiteOpL<NS>& sA,
+                                           const SiteOpL<NS>& sB, cpx<R> (*xl)[256], cpx<R> (*xch)[3][256],
+                                           cpx<R> (*carry)[3][512], int i, int st, int t0, int TC, int s, int lane,
+                                           int ls, int q) {
+    const int tid = threadIdx.x;
+    tws_carry<NS, DAG, H>(&carry[0][0][tid], a.in, a.Uoth, i + st * (t0 == 0 ? a.g.Lt - 1 : t0 - 1), s);
+    tws_carry<NS, DAG, H>(&carry[1][0][tid], a.in, a.Uoth, i + st * t0, s);
+    {   // slab t0's columns (this half's spins); published by the first step's barriers
+        cpx<R> up[3], dn[3];
+        load_spins<NS, H, H>(up, dn, a.in, (size_t)(i + st * t0), s);
+#pragma unroll
+        for (int c = 0; c < 3; c++) { xl[3 * H + c][q] = up[c]; xl[6 + 3 * H + c][q] = dn[c]; }
+    }
+    double nrm = 0.0;
+    for (int k = 0; k < TC; k++)
+        tws_step<NS, DAG, MODE, RED, H>(a, sU, sA, sB, i + st * (t0 + k), s, lane, ls, q, &carry[k & 1][0][tid], nrm,
+                                        xl, xch);
+    return nrm;
+}
+
+template <int NS, bool DAG, int MODE, bool RED, typename R>
+__global__ __launch_bounds__(512, 1) void k_hop_tws(const HopArgs<R> a) {
+    if (a.done && *a.done != 0.0) return;
+    __shared__ cpx<R> sU[256 / NS][8][9];
+    __shared__ cpx<R> xl[12][256];       // the current slab's input columns of this segment
+    __shared__ cpx<R> xch[2][3][256];    // lower-spin partial sums handed between the halves
+    __shared__ cpx<R> carry[2][3][512];  // carried backward t terms (slot t % 2 for slab t), per lane
+    __shared__ SiteOpL<NS> sA, sB;
+    {
+        OpsShare<NS> sh;
+        ops_fetch<NS, MODE>(sh, a);
+        ops_store<NS, MODE>(sA, sB, sh);  // published by the first step's barriers
+    }
+    const int nseg = (int)((size_t)a.g.Vh / a.g.Lt * NS / 256);
+    int seg, chunk;
+    tw_tile(blockIdx.x, gridDim.x, a.sc, nseg, seg, chunk);
+    const int q = threadIdx.x & 255;            // site-lane of the segment
+    const int lane = threadIdx.x & 63, s = q % NS, ls = q / NS;
+    const int st = a.g.Vh / a.g.Lt;             // sites per slab
+    const int i = seg * (256 / NS) + ls;        // slab index of this lane's site
+    const int TC = a.sc.tt, t0 = chunk * TC;
+    // the two halves run the same sequence of barriers; the branch is uniform per wave
+    const double nrm = threadIdx.x < 256
+        ? tws_walk<NS, DAG, MODE, RED, 0>(a, sU, sA, sB, xl, xch, carry, i, st, t0, TC, s, lane, ls, q)
+        : tws_walk<NS, DAG, MODE, RED, 1>(a, sU, sA, sB, xl, xch, carry, i, st, t0, TC, s, lane, ls, q);
+    if constexpr (RED || MODE == HM_SCHUR_W) {
+        __shared__ double lds[8];
+        finish_sum(a.red, block_sum512(nrm, lds));
+    }
+}
+
 // ===================================================================== multi-RHS hop
 // With H (R = float only) the Krylov fields in, out (not HM_SCHUR_Q), out2 and aux are FP16 columns;
 // the residual (aux2 and the output of HM_SCHUR_Q) stays FP32.
@@ -1044,8 +1383,9 @@ hipError_t launch_maxpy(const cd* const* v, const double* cr, const double* ci, 
 
 // Whether schedule sc (mode 3 or 5) fits the lattice and Ns; the t-walk grid size when it does, else 0.
 int tw_grid(const Geom& g, int Ns, const Sched& sc) {
-    if ((sc.mode != 3 && sc.mode != 5) || Ns < 8) return 0;
-    if (sc.mode == 5 && (256 / Ns) % g.Lxh) return 0;  // the segment must hold whole x-lines
+    if ((sc.mode != 3 && sc.mode != 5 && sc.mode != 6) || Ns < 8) return 0;
+    if (sc.mode == 6 && Ns != 16) return 0;  // the spin-split form is built for Ns = 16
+    if (sc.mode >= 5 && (256 / Ns) % g.Lxh) return 0;  // the segment must hold whole x-lines
     const long slab = (long)g.Vh / g.Lt;
     if ((slab * Ns) % 256 != 0) return 0;
     const long nseg = slab * Ns / 256;
@@ -1065,12 +1405,18 @@ template <typename K> static size_t lds_room(K kern) {
 template <typename R>
 hipError_t launch_hop(int Ns, bool dag, int mode, bool red, const HopArgs<R>& a, hipStream_t st) {
     const size_t nthreads = (size_t)a.g.Vh * Ns;
-    const bool tw = a.sc.mode == 3 || a.sc.mode == 5;
+    const bool tw = a.sc.mode == 3 || a.sc.mode == 5 || a.sc.mode == 6;
     const int grid = tw ? tw_grid(a.g, Ns, a.sc) : (int)((nthreads + 255) / 256);
     if (grid <= 0) return hipErrorInvalidValue;
     const size_t pad = tw ? (size_t)a.sc.ord * 1024 : 0;  // LDS reserved to cap workgroups per CU
 #define HOP_L(D, M, RD)                                                                                  \
     do {                                                                                                 \
+        if constexpr (NS == 16) {                                                                        \
+            if (tw && a.sc.mode == 6) {                                                                  \
+                hipLaunchKernelGGL((k_hop_tws<NS, D, M, RD, R>), dim3(grid), dim3(512), 0, st, a);          \
+                break;                                                                                   \
+            }                                                                                            \
+        }                                                                                                \
         if constexpr (NS >= 8) {                                                                         \
             if (tw && a.sc.mode == 5) {                                                                  \
                 static const size_t room = lds_room(k_hop_tw<NS, D, M, RD, R, true>);                    \

@@ -51,6 +51,8 @@ def source_sha1():
 
 def hop_kernel_name(sched):
     """Kernel-name prefix of the FP64 K1 hop (u = A_T^{-1} H_eo p, HM_SITE = 1) under schedule sched."""
+    if sched[0] == 6:
+        return "eofa::k_hop_tws<16, false, 1, false, double>"
     if sched[0] == 5:
         return "eofa::k_hop_tw<16, false, 1, false, double, true>"
     if sched[0] == 3:
@@ -136,7 +138,7 @@ def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, dims=(32, 32, 
            "source_files": KERNEL_SOURCES}
 
     def hops(rows):
-        return [v for nm, v in rows if re.search(r"k_hop(_tw)?<16, false, 1, false, double", nm)]
+        return [v for nm, v in rows if re.search(r"k_hop(_tws?)?<16, false, 1, false, double", nm)]
     hf, hw = hops(f), hops(w)
     # profile_hop.py: per schedule, 2 untimed + nrep timed launches; keep the nrep timed ones
     per = nrep + 2
@@ -145,7 +147,7 @@ def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, dims=(32, 32, 
         wk = hw[i * per + 2:(i + 1) * per]
         rd = ff * 1024 * sum(fk) / len(fk)
         wr = wf * 1024 * sum(wk) / len(wk)
-        res["by_schedule"][s] = {"kernel": "k_hop_tw" if s.startswith(("3,", "5,")) else "k_hop",
+        res["by_schedule"][s] = {"kernel": {"3": "k_hop_tw", "5": "k_hop_tw", "6": "k_hop_tws"}.get(s.split(",")[0], "k_hop"),
                                  "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
                                  "read_bytes_per_launch": round(rd), "write_bytes_per_launch": round(wr),
                                  "bytes_per_launch": round(rd + wr), "amplification": round((rd + wr) / alg, 4)}

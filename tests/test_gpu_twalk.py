@@ -1,4 +1,4 @@
-"""The t-walk hop schedules (workgroups walking t with the backward t term carried, modes 3 and 5) against the
+"""The t-walk hop schedules (workgroups walking t with the backward t term carried, modes 3, 5 and 6) against the
 default schedule and the oracle: every operator bit-for-bit equal to the default schedule's in FP64 and
 FP32 for every t-walk schedule the autotuner may pick, the FP64 D_T against the oracle, and a CG solve
 under a t-walk schedule checked by the oracle's residual."""
@@ -17,7 +17,7 @@ OPS = ["DW", "HOP", "DT", "DT_DAG", "HT", "AT_INV", "SCHUR", "SCHUR_DAG", "SCHUR
 
 
 def tw_schedules(dims, Ns):
-    """The t-walk candidates of the autotuner: [3 or 5, xcd, ty, tz, tt, nyb, KB of reserved LDS]."""
+    """The t-walk candidates of the autotuner: [3, 5 or 6, xcd, ty, tz, tt, nyb, KB of reserved LDS]."""
     Lxh, Ly, Lz, Lt = dims[0] // 2, dims[1], dims[2], dims[3]
     if (Lxh * Ly * Ns) % 256:
         return []
@@ -31,8 +31,12 @@ def tw_schedules(dims, Ns):
                 if Lt % tt:
                     continue
                 for pad in (0, 48):
-                    for mode in (3, 5):  # 5: x neighbours from LDS, segments of whole x-lines
-                        if mode == 5 and (256 // Ns) % Lxh:
+                    # 5: x neighbours from LDS, segments of whole x-lines; 6: the same with the spin-split lanes
+                    # (Ns = 16); both hold a CU's LDS, so they take no reserve
+                    for mode in (3, 5, 6):
+                        if mode >= 5 and ((256 // Ns) % Lxh or pad):
+                            continue
+                        if mode == 6 and Ns != 16:
                             continue
                         out.append([mode, 1, ty, tz, tt, nyb, pad])
     return out
