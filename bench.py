@@ -86,6 +86,34 @@ def measured_traffic(path, dims, Ns, sched):
         return None
 
 
+def learned_leg(E, IN, ctx, Ns, omega, eps, action, phi_d, plain, max_iter):
+    """The learned preconditioner on the step's action: the network is trained on the GPU (forward, backward and
+    Adam kernels of the library) on residual->error pairs from CG iterates of 4 seeded 8^4 fields (the network
+    is translation invariant), then used as the right preconditioner of flexible GCR with CG as its fallback,
+    FP64, to the same true residual; its time is compared with the plain FP64 CG solve of the same action."""
+    from paper_1710_09621_amd import learned as LRN
+    t0 = time.perf_counter()
+    small = (8, 8, 8, 8)
+    ctx_t = E.Context(small, Ns, IN.M0, omega, device="cuda:0")
+    fields = [(s, IN.gauge_links(small, eps, s)) for s in range(40, 44)]
+    hist = LRN.train(ctx_t, fields, action[1], action[2], steps=400, lr=2e-4, lr_end=2e-5, n_cg=8, n_rand=0)
+    ctx.set_precond(ctx_t.cnn_params())
+    del ctx_t
+    t1 = time.perf_counter()
+    r = ctx.chiral_action(*action, phi_d, E.params(tol=1e-10, max_iter=max_iter, pc=E.PC_LEARNED))
+    t2 = time.perf_counter()
+    i = r.info[0]
+    log(f"  [learned] action {action}: iters={i['iters']} fell_back={i['fell_back']} resid={i['true_rel_resid']:.2e} "
+        f"{t2 - t1:.2f}s against plain {plain.info[0]['seconds']:.2f}s (training {t1 - t0:.1f}s)")
+    return {"action": list(action), "s": round(t2 - t1, 3), "iters": i["iters"], "fell_back": i["fell_back"],
+            "true_rel_resid": i["true_rel_resid"], "plain_fp64_s": round(plain.info[0]["seconds"], 3),
+            "plain_iters": plain.info[0]["iters"], "speedup_vs_plain": round(plain.info[0]["seconds"] / (t2 - t1), 3),
+            "max_rel_dS": abs(r.S - plain.S) / abs(plain.S), "training_s": round(t1 - t0, 1),
+            "final_loss": float(sum(hist[-50:]) / 50),
+            "form": "flexible GCR with the 4-layer BF16 convolutional network, FP64, CG fallback; trained on "
+                    "CG-iterate residual->error pairs of 4 seeded 8^4 fields (400 Adam steps)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +123,7 @@ def main():
     ap.add_argument("--config", type=int, default=5)
     ap.add_argument("--no-tts", action="store_true", help="skip the once-per-run time-to-solution comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg of the time to solution")
     ap.add_argument("--max-iter", type=int, default=50000)
     ap.add_argument("--tune-cache", type=str, default=None)
     ap.add_argument("--tuned-prec", choices=("fp16", "fp32"), default="fp16",
@@ -204,6 +233,8 @@ def main():
                "speedup": round((tb - ta) / (tc - tb), 3), "max_true_rel_resid": max(resid), "max_rel_dS": dS,
                "sources": 1}
         log(f"time to solution: plain {tb - ta:.2f}s, tuned {tc - tb:.2f}s ({tts['speedup']:.2f}x)")
+        if not args.no_learned:
+            tts["learned"] = learned_leg(E, IN, ctx, Ns, omega, eps, step_action, phi_d, plain[1], args.max_iter)
 
     sched64 = tune["fp64"]["sched"]
     traffic = measured_traffic(args.traffic, dims, Ns, sched64)

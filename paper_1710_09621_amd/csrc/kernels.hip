@@ -94,8 +94,41 @@ __device__ __forceinline__ void store_col(void* __restrict__ f, size_t cb, int s
     }
 }
 
+// An FP16 column of a field in storage H without its norm (p = raw binary16 values widened) and the norm n.
+template <int NS>
+__device__ __forceinline__ float load_h_raw(cpx<float> p[12], const void* __restrict__ f, size_t cb, int s, int Vh) {
+    const h8_t* d = (const h8_t*)f + cb * 3 * NS + s;
+#pragma unroll
+    for (int jb = 0; jb < 3; jb++) {
+        const h8_t v = d[jb * NS];
+#pragma unroll
+        for (int k = 0; k < 4; k++) p[4 * jb + k] = {(float)v[2 * k], (float)v[2 * k + 1]};
+    }
+    return h_norms<NS>(f, Vh)[cb * NS + s];
+}
+
+// reconstruct() of n w: the column norm of an FP16 neighbour folded into the accumulation (one FMA per real
+// instead of a multiply on every loaded component and an add)
+template <int MU, int S, typename R>
+__device__ __forceinline__ void reconstruct_n(cpx<R> acc[12], const cpx<R> w[6], R n) {
+    const R sn = S > 0 ? n : -n;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cpx<R> w0 = w[c], w1 = w[3 + c], t0, t1;  // t = B^dag w
+        if constexpr (MU == 0) { t0 = ci(w1); t1 = ci(w0); }
+        else if constexpr (MU == 1) { t0 = w1; t1 = cneg(w0); }
+        else if constexpr (MU == 2) { t0 = ci(w0); t1 = cneg(ci(w1)); }
+        else { t0 = w0; t1 = w1; }
+        acc[c].x = fma(n, w0.x, acc[c].x); acc[c].y = fma(n, w0.y, acc[c].y);
+        acc[3 + c].x = fma(n, w1.x, acc[3 + c].x); acc[3 + c].y = fma(n, w1.y, acc[3 + c].y);
+        acc[6 + c].x = fma(sn, t0.x, acc[6 + c].x); acc[6 + c].y = fma(sn, t0.y, acc[6 + c].y);
+        acc[9 + c].x = fma(sn, t1.x, acc[9 + c].x); acc[9 + c].y = fma(sn, t1.y, acc[9 + c].y);
+    }
+}
+
 // One direction mu of the hop: forward (1 - S gamma) U in(x+mu) and backward (1 + S gamma) U^dag in(x-mu).
-// Uf / Ub point at the 9 complex entries of U_mu(x) and U_mu(x-mu) (global memory or LDS).
+// Uf / Ub point at the 9 complex entries of U_mu(x) and U_mu(x-mu) (global memory or LDS).  FP16 columns (H)
+// are projected and multiplied unscaled; their norm enters in the accumulation.
 template <int NS, bool DAG, int MU, typename R, bool H = false>
 __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict__ in, const cpx<R>* Uf,
                                        const cpx<R>* Ub, const int nb[8], int s, int Vh = 0) {
@@ -103,23 +136,29 @@ __device__ __forceinline__ void hop_mu(cpx<R> acc[12], const cpx<R>* __restrict_
     constexpr int SB = -SF;
     {
         cpx<R> p[12];
-        load_col<NS, H>(p, in, (size_t)nb[2 * MU], s, Vh);
+        R n = 1;
+        if constexpr (H) n = load_h_raw<NS>(p, in, (size_t)nb[2 * MU], s, Vh);
+        else load_col<NS, H>(p, in, (size_t)nb[2 * MU], s, Vh);
         cpx<R> h[6], w[6], U[9];
         project<MU, SF>(p, h);
 #pragma unroll
         for (int k = 0; k < 9; k++) U[k] = Uf[k];
         link_mul<false>(U, h, w);
-        reconstruct<MU, SF>(acc, w);
+        if constexpr (H) reconstruct_n<MU, SF>(acc, w, n);
+        else reconstruct<MU, SF>(acc, w);
     }
     {
         cpx<R> p[12];
-        load_col<NS, H>(p, in, (size_t)nb[2 * MU + 1], s, Vh);
+        R n = 1;
+        if constexpr (H) n = load_h_raw<NS>(p, in, (size_t)nb[2 * MU + 1], s, Vh);
+        else load_col<NS, H>(p, in, (size_t)nb[2 * MU + 1], s, Vh);
         cpx<R> h[6], w[6], U[9];
         project<MU, SB>(p, h);
 #pragma unroll
         for (int k = 0; k < 9; k++) U[k] = Ub[k];
         link_mul<true>(U, h, w);
-        reconstruct<MU, SB>(acc, w);
+        if constexpr (H) reconstruct_n<MU, SB>(acc, w, n);
+        else reconstruct<MU, SB>(acc, w);
     }
 }
 
