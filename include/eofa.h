@@ -87,7 +87,11 @@ typedef enum {
     EOFA_OP_AT_INV = 5,    /* (4 - m0 + P_+ M_+ + P_- M_-)^{-1}, site-local */
     EOFA_OP_SCHUR = 6,     /* Dhat = 1 - A^{-1}(D_T)_oe A^{-1}(D_T)_eo on odd sites (even sites of out = 0) */
     EOFA_OP_SCHUR_DAG = 7, /* Dhat^dagger */
-    EOFA_OP_SCHUR_NORMAL = 8 /* Dhat^dagger Dhat */
+    EOFA_OP_SCHUR_NORMAL = 8, /* Dhat^dagger Dhat */
+    EOFA_OP_DODWF = 9,     /* D_odwf(m+, m-) = D_w omega (1 + L) + (1 - L), the optimal DWF operator (Sec. III.A) */
+    EOFA_OP_DODWF_DAG = 10, /* D_odwf(m+, m-)^dagger */
+    EOFA_OP_HOP_EO = 11,   /* Wilson hop from the odd to the even sites (odd sites of out = 0) */
+    EOFA_OP_HOP_OE = 12    /* Wilson hop from the even to the odd sites (even sites of out = 0) */
 } eofa_op;
 
 /*

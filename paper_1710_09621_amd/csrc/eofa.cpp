@@ -1652,7 +1652,7 @@ template <typename R> struct ApplyBufs {
     cpx<R>* in[2];
     cpx<R>* out[2];
     cpx<R> *u, *w, *wt, *at;
-    const SiteOp* tab[4];  // site-operator tables by SiteKind for (mp, mm); a null entry is taken from site_tab
+    const SiteOp* tab[SK_NKIND];  // site-operator tables by SiteKind for (mp, mm); a null entry is taken from site_tab
     double* partials;      // reduction buffers of the Schur kernels (null: the context's)
     double* scal;
 };
@@ -1684,6 +1684,46 @@ void apply_op(eofa_ctx* ctx, int op, double mp, double mm, const cd* in, cd* out
     case EOFA_OP_AT_INV: {
         const SiteOp* Ai = tab(SK_AINV);
         for (int par = 0; par < 2; par++) HIPCHK(launch_site<R>(Ns, false, B.in[par], B.out[par], Ai, ctx->g.Vh, ctx->st));
+        break;
+    }
+    case EOFA_OP_DODWF: {  // D_odwf in = A in - (1/2) H omega (1 + L) in
+        const SiteOp* A = tab(SK_A);
+        const SiteOp* W = tab(SK_OM1L);
+        cpx<R>* v[2] = {B.u, B.w};
+        cpx<R>* a[2] = {B.wt, B.at};
+        for (int par = 0; par < 2; par++) {
+            HIPCHK(launch_site<R>(Ns, false, B.in[par], v[par], W, ctx->g.Vh, ctx->st));
+            HIPCHK(launch_site<R>(Ns, false, B.in[par], a[par], A, ctx->g.Vh, ctx->st));
+        }
+        for (int par = 0; par < 2; par++) {
+            auto h = hop_args<R>(ctx, par);
+            h.in = v[1 - par]; h.out = B.out[par]; h.aux = a[par]; h.caux = 1; h.cz = (R)-0.5;
+            hop<R>(ctx, false, HM_LIN, false, h);
+        }
+        break;
+    }
+    case EOFA_OP_DODWF_DAG: {  // D_odwf^dag in = A^dag in - (1/2) (1 + L)^dag omega gamma_5 H gamma_5 in
+        const SiteOp* Ad = tab(SK_A_DAG);
+        const SiteOp* Wd = tab(SK_OM1L_DAG);
+        cpx<R>* t[2] = {B.u, B.w};
+        for (int par = 0; par < 2; par++) {
+            auto h = hop_args<R>(ctx, par);
+            h.in = B.in[1 - par]; h.out = t[par]; h.opA = Wd; h.cz = (R)-0.5; h.caux = 0;
+            hop<R>(ctx, true, HM_SITE, false, h);
+        }
+        for (int par = 0; par < 2; par++) {
+            HIPCHK(launch_site<R>(Ns, true, B.in[par], B.out[par], Ad, ctx->g.Vh, ctx->st));
+            HIPCHK(launch_axpby<R>((R)1, t[par], (R)1, B.out[par], nh, nullptr, ctx->st));
+        }
+        break;
+    }
+    case EOFA_OP_HOP_EO:
+    case EOFA_OP_HOP_OE: {  // the hop into one parity from the other; the input's own parity is not read
+        const int par = op == EOFA_OP_HOP_EO ? 0 : 1;
+        auto h = hop_args<R>(ctx, par);
+        h.in = B.in[1 - par]; h.out = B.out[par]; h.cz = 1; h.caux = 0;
+        hop<R>(ctx, false, HM_LIN, false, h);
+        HIPCHK(launch_fill0(B.out[1 - par], nh * sizeof(cpx<R>), ctx->st));
         break;
     }
     default: {  // SCHUR, SCHUR_DAG, SCHUR_NORMAL
@@ -1725,7 +1765,20 @@ void check_apply(eofa_ctx* ctx, int op, const void* in, const void* out, int pre
     REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
     REQUIRE(in && out && in != out, EOFA_EINVAL, "bad field pointers");
     REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32, EOFA_EINVAL, "prec must be EOFA_FP64 or EOFA_MIXED_FP32");
-    REQUIRE(op >= EOFA_OP_DW && op <= EOFA_OP_SCHUR_NORMAL, EOFA_EINVAL, "unknown op");
+    REQUIRE(op >= EOFA_OP_DW && op <= EOFA_OP_HOP_OE, EOFA_EINVAL, "unknown op");
+}
+
+// the site-operator tables apply_op reads for op
+std::vector<SiteKind> op_kinds(int op) {
+    switch (op) {
+    case EOFA_OP_DT_DAG: return {SK_M_DAG};
+    case EOFA_OP_AT_INV: return {SK_AINV};
+    case EOFA_OP_SCHUR: case EOFA_OP_SCHUR_DAG: case EOFA_OP_SCHUR_NORMAL: return {SK_AINV, SK_AINV_DAG};
+    case EOFA_OP_DODWF: return {SK_A, SK_OM1L};
+    case EOFA_OP_DODWF_DAG: return {SK_A_DAG, SK_OM1L_DAG};
+    case EOFA_OP_HOP_EO: case EOFA_OP_HOP_OE: return {};
+    default: return {SK_M};  // DW, HOP, DT, HT
+    }
 }
 
 }  // namespace
@@ -1971,29 +2024,32 @@ eofa_status eofa_apply_static(eofa_ctx* ctx, int op, double m_plus, double m_min
         auto take = [&](size_t n) { char* r = q; q += n; return r; };
         void* h[8];
         for (void*& v : h) v = take(hb);
-        // the site-operator tables this op reads, built on the host and written by kernels
-        const SiteOp* tabs[4] = {nullptr, nullptr, nullptr, nullptr};
-        const bool schur = op >= EOFA_OP_SCHUR, dt = op == EOFA_OP_DW || op == EOFA_OP_HOP || op == EOFA_OP_DT ||
-                                                        op == EOFA_OP_DT_DAG || op == EOFA_OP_HT;
-        const bool used[4] = {schur || op == EOFA_OP_AT_INV, schur, dt && op != EOFA_OP_DT_DAG, op == EOFA_OP_DT_DAG};
-        for (int k = 0; k < 4; k++) {
+        // the site-operator tables this op reads (at most 4), built on the host and written by kernels
+        ApplyBufs<double> B64{};
+        ApplyBufs<float> B32{};
+        const std::vector<SiteKind> kinds = op_kinds(op);
+        for (size_t i = 0; i < 4; i++) {
             double* d = (double*)take(tb);
-            if (!used[k]) continue;
+            if (i >= kinds.size()) continue;
             SiteOp host;
-            build_site_op(host, (SiteKind)k, ctx->Ns, ctx->m0, ctx->omega.data(), m_plus, m_minus);
+            build_site_op(host, kinds[i], ctx->Ns, ctx->m0, ctx->omega.data(), m_plus, m_minus);
             HIPCHK(launch_set_block(d, sizeof(SiteOp) / sizeof(double), (const double*)&host, ctx->st));
-            tabs[k] = (const SiteOp*)d;
+            B64.tab[kinds[i]] = B32.tab[kinds[i]] = (const SiteOp*)d;
         }
         double* partials = (double*)take(pb);
         double* scal = (double*)take(sb);
         if (prec == EOFA_FP64) {
-            ApplyBufs<double> B{{(cd*)h[0], (cd*)h[1]}, {(cd*)h[2], (cd*)h[3]}, (cd*)h[4], (cd*)h[5], (cd*)h[6], (cd*)h[7],
-                                {tabs[0], tabs[1], tabs[2], tabs[3]}, partials, scal};
+            ApplyBufs<double>& B = B64;
+            B.in[0] = (cd*)h[0]; B.in[1] = (cd*)h[1]; B.out[0] = (cd*)h[2]; B.out[1] = (cd*)h[3];
+            B.u = (cd*)h[4]; B.w = (cd*)h[5]; B.wt = (cd*)h[6]; B.at = (cd*)h[7];
+            B.partials = partials; B.scal = scal;
             apply_op<double>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
         } else {
             using cf = cpx<float>;
-            ApplyBufs<float> B{{(cf*)h[0], (cf*)h[1]}, {(cf*)h[2], (cf*)h[3]}, (cf*)h[4], (cf*)h[5], (cf*)h[6], (cf*)h[7],
-                               {tabs[0], tabs[1], tabs[2], tabs[3]}, partials, scal};
+            ApplyBufs<float>& B = B32;
+            B.in[0] = (cf*)h[0]; B.in[1] = (cf*)h[1]; B.out[0] = (cf*)h[2]; B.out[1] = (cf*)h[3];
+            B.u = (cf*)h[4]; B.w = (cf*)h[5]; B.wt = (cf*)h[6]; B.at = (cf*)h[7];
+            B.partials = partials; B.scal = scal;
             apply_op<float>(ctx, op, m_plus, m_minus, (const cd*)in, (cd*)out, B);
         }
         HIPCHK(hipGetLastError());

@@ -134,8 +134,10 @@ hipError_t launch_combine(const cd* phi, const cd* xh, cd* out, const Geom& g, i
                           const double* Om, int accumulate, const Red& red, hipStream_t st);
 
 // ---- site-local operator tables (sitetab.cpp)
-enum SiteKind : int { SK_AINV = 0, SK_AINV_DAG = 1, SK_M = 2, SK_M_DAG = 3 };
-// Fill op with the tables of A_T^{-1}, A_T^{-dag}, M or M^T for masses (mp, mm).
+enum SiteKind : int { SK_AINV = 0, SK_AINV_DAG = 1, SK_M = 2, SK_M_DAG = 3, SK_A = 4, SK_A_DAG = 5, SK_OM1L = 6,
+                      SK_OM1L_DAG = 7, SK_NKIND = 8 };
+// Fill op with the tables of A_T^{-1}, A_T^{-dag}, M, M^T, A, A^T, omega (1 + L) or (1 + L)^T omega for masses
+// (mp, mm).
 void build_site_op(SiteOp& op, SiteKind kind, int Ns, double m0, const double* omega, double mp, double mm);
 
 }  // namespace eofa

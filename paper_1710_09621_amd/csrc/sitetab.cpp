@@ -10,6 +10,8 @@
 //
 //   A_T^{-1} = omega^{1/2} (1 + L) A^{-1} omega^{1/2},   A = (4 - m0) omega (1 + L) + (1 - L)
 //   M        = omega^{-1/2} (1 - L) (1 + L)^{-1} omega^{-1/2}
+//   A, omega (1 + L) and their transposes (shift only: the scan tables stay zero), for
+//   D_odwf = A - (1/2) H omega (1 + L) and D_odwf^dag = A^dag - (1/2) (1 + L)^dag omega H^dag
 // (A_T = 4 - m0 + M is the x-diagonal block of D_T in Eq.(DTm1m2); A is the same block of the
 // optimal-DWF operator, A_T = omega^{-1/2} A (1 + L)^{-1} omega^{-1/2}), and their transposes.
 #include <cmath>
@@ -48,7 +50,7 @@ double fill_scan(ChirTab& t, const Ring& r, const double* c) {
 
 void build_half(ChirTab& t, SiteKind kind, int Ns, double m0, const double* om, double m, int sigL) {
     std::memset(&t, 0, sizeof(t));
-    const bool dag = (kind == SK_AINV_DAG || kind == SK_M_DAG);
+    const bool dag = (kind == SK_AINV_DAG || kind == SK_M_DAG || kind == SK_A_DAG || kind == SK_OM1L_DAG);
     Ring r{Ns, dag ? -sigL : sigL, -m};
     double c[MAXNS], kappa;
     switch (kind) {
@@ -75,6 +77,28 @@ void build_half(ChirTab& t, SiteKind kind, int Ns, double m0, const double* om, 
         }
         kappa = fill_scan(t, r, c);
         for (int s = 0; s < Ns; s++) t.post[s] = std::sqrt(om[s]) * kappa;
+        break;
+    }
+    case SK_A:        // A = (4 - m0) omega (1 + L) + (1 - L): y_s = a_s x_s + b_s tw x_{s+sig}, no solve
+    case SK_A_DAG: {  // A^dag: y_s = a_s x_s + b_{s+sig} tw x_{s+sig}
+        for (int s = 0; s < Ns; s++) {
+            const double a = (4.0 - m0) * om[s] + 1.0;
+            const double b = (4.0 - m0) * om[dag ? r.nb(s) : s] - 1.0;
+            t.pre[s] = 1.0;
+            t.mid[s] = 1.0;
+            t.shf[s] = b * r.tw(s) / a;
+            t.post[s] = a;
+        }
+        break;
+    }
+    case SK_OM1L:        // omega (1 + L): y_s = omega_s (x_s + tw x_{s+sig})
+    case SK_OM1L_DAG: {  // (1 + L)^dag omega: y_s = omega_s x_s + tw omega_{s+sig} x_{s+sig}
+        for (int s = 0; s < Ns; s++) {
+            t.pre[s] = dag ? om[s] : 1.0;
+            t.mid[s] = 1.0;
+            t.shf[s] = r.tw(s);
+            t.post[s] = dag ? 1.0 : om[s];
+        }
         break;
     }
     case SK_M:

@@ -24,7 +24,8 @@ FP64, MIXED_FP32, MIXED_FP16 = 0, 1, 2
 PC_NONE, PC_LEARNED = 0, 1
 CNN_NPARAM = 4 * (81 * 32 * 32 + 32)
 HB_BATCH = 8  # the heat-bath's shifted solves run as one multi-RHS batch of at most 8 systems
-OPS = dict(DW=0, HOP=1, DT=2, DT_DAG=3, HT=4, AT_INV=5, SCHUR=6, SCHUR_DAG=7, SCHUR_NORMAL=8)
+OPS = dict(DW=0, HOP=1, DT=2, DT_DAG=3, HT=4, AT_INV=5, SCHUR=6, SCHUR_DAG=7, SCHUR_NORMAL=8, DODWF=9, DODWF_DAG=10,
+           HOP_EO=11, HOP_OE=12)
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "ESTATE", -6: "ENOTIMPL"}
 
 

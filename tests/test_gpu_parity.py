@@ -30,6 +30,29 @@ def test_dt_and_friends(setup, mp, mm):
     assert relerr(ctx.apply("AT_INV", x, mp, mm), lat.at_inv(x, mp, mm)) < 1e-12
 
 
+@pytest.mark.parametrize("mp,mm", MASSES)
+def test_dodwf(setup, mp, mm):
+    """The optimal-DWF operator D_odwf = D_w omega (1 + L) + (1 - L) and its adjoint (the oracle forms them from
+    the definition; the library from A - (1/2) H omega (1 + L) with site-local tables)."""
+    ctx, lat = setup
+    x = rand5(lat, 7)
+    assert relerr(ctx.apply("DODWF", x, mp, mm), lat.dodwf(x, mp, mm)) < 1e-12
+    assert relerr(ctx.apply("DODWF_DAG", x, mp, mm), lat.dodwf(x, mp, mm, dag=True)) < 1e-12
+
+
+def test_parity_hops(setup):
+    """H_eo and H_oe: the hop of the odd (even) half into the even (odd) sites; the other half of out is zero
+    and the input's own half is not read."""
+    from oracle import oracle as O
+    ctx, lat = setup
+    x = rand5(lat, 8)
+    odd = O.parity_mask(lat.dims)[None, ..., None, None]
+    hop = lambda f: np.stack([lat.hop(f[s]) for s in range(lat.Ns)])
+    assert relerr(ctx.apply("HOP_EO", x), hop(x * odd) * ~odd) < 1e-12
+    assert relerr(ctx.apply("HOP_OE", x), hop(x * ~odd) * odd) < 1e-12
+    assert np.all(ctx.apply("HOP_EO", x).cpu().numpy()[np.broadcast_to(odd, x.shape)] == 0)
+
+
 def test_dw_and_hop(setup):
     ctx, lat = setup
     x = rand5(lat, 4)

@@ -9,7 +9,8 @@ from gpu_common import ctx_and_oracle, rand5, relerr
 
 pytestmark = pytest.mark.gpu
 
-OPS = ["DW", "HOP", "DT", "DT_DAG", "HT", "AT_INV", "SCHUR", "SCHUR_DAG", "SCHUR_NORMAL"]
+OPS = ["DW", "HOP", "DT", "DT_DAG", "HT", "AT_INV", "SCHUR", "SCHUR_DAG", "SCHUR_NORMAL", "DODWF", "DODWF_DAG",
+       "HOP_EO", "HOP_OE"]
 
 
 @pytest.mark.parametrize("prec", ["FP64", "MIXED_FP32"])
