@@ -81,7 +81,7 @@ def measured_traffic(path, dims, Ns, sched):
         if entry is None:
             log(f"no counter summary for schedule {sched}: traffic = null")
             return None
-        return round(float(entry["bytes_per_launch"]))
+        return round(float(entry[t["by_schedule_fields"].index("bytes_per_launch")]))
     except (OSError, KeyError, ValueError):
         return None
 

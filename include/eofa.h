@@ -272,13 +272,20 @@ eofa_status eofa_dslash_bench(eofa_ctx *ctx, int prec, int nrep, double *ms, dou
  * nrep launches of the fused hop (0: 4) and keeps the fastest for all later solves.  Every
  * schedule gives bitwise the same operator; the CG reductions may sum in another order.
  * sched_out[7] (may be NULL) receives {mode, xcd, ty, tz, tt, nyb, ord} for a persistent cache
- * (mode 0: linear, 1: 3D tiles, 3: t-walk, 5: t-walk with the x neighbours from LDS);
+ * (mode 0: linear, 1: 3D tiles, 3: t-walk, 5: t-walk with the x neighbours from LDS, 6: mode 5 with
+ * two lanes per site and slice, Ns = 16);
  * *best_ms / *base_ms (may be NULL) the chosen and the linear-order launch times.
  */
 eofa_status eofa_autotune(eofa_ctx *ctx, int prec, int nrep, int sched_out[7], double *best_ms,
                           double *base_ms);
 /* Re-install a schedule returned by eofa_autotune (EINVAL if it does not fit this lattice). */
 eofa_status eofa_set_schedule(eofa_ctx *ctx, int prec, const int sched_in[7]);
+/*
+ * The schedules eofa_autotune times for this lattice and storage precision, in its order: the first
+ * min(max, count) of them go to sched_out as rows of 7 ints (host memory, 7 * max ints; may be NULL
+ * when max = 0), the count to *n.  No GPU work.  EINVAL for a bad prec, a null n or max < 0.
+ */
+eofa_status eofa_schedule_candidates(eofa_ctx *ctx, int prec, int max, int *sched_out, int *n);
 
 /*
  * Learned preconditioner (solves with params->pc = EOFA_PC_LEARNED; Ns must be a multiple of 8).

@@ -2202,6 +2202,22 @@ eofa_status eofa_set_schedule(eofa_ctx* ctx, int prec, const int sched_in[7]) {
     });
 }
 
+eofa_status eofa_schedule_candidates(eofa_ctx* ctx, int prec, int max, int* sched_out, int* n) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(n && max >= 0 && (sched_out || max == 0), EOFA_EINVAL, "null count, or null rows with max > 0");
+        REQUIRE(prec == EOFA_FP64 || prec == EOFA_MIXED_FP32 || prec == EOFA_MIXED_FP16, EOFA_EINVAL,
+                "prec must be FP64, MIXED_FP32 or MIXED_FP16");
+        const std::vector<Sched> c = sched_candidates(ctx, prec);
+        for (int i = 0; i < max && i < (int)c.size(); i++) {
+            int* r = sched_out + 7 * i;
+            r[0] = c[i].mode; r[1] = c[i].xcd; r[2] = c[i].ty; r[3] = c[i].tz;
+            r[4] = c[i].tt; r[5] = c[i].nyb; r[6] = c[i].ord;
+        }
+        *n = (int)c.size();
+        return EOFA_OK;
+    });
+}
+
 eofa_status eofa_set_precond(eofa_ctx* ctx, const float* params_host, size_t count, int relu) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(params_host && count == (size_t)CNN_NPARAM, EOFA_EINVAL,

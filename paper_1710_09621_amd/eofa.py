@@ -115,6 +115,7 @@ def load():
         "eofa_dslash_bench": [P, I, I, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "eofa_autotune": [P, I, I, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "eofa_set_schedule": [P, I, C.POINTER(C.c_int)],
+        "eofa_schedule_candidates": [P, I, I, C.POINTER(C.c_int), C.POINTER(C.c_int)],
         "eofa_last_error": [P],
         "eofa_destroy": [P],
     }
@@ -133,7 +134,7 @@ def exported_symbols():
     lib = load()
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
                         "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht", "eofa_solve_ht_batch", "eofa_chiral_heatbath", "eofa_heatbath",
-                        "eofa_inv_sqrt_rational",
+                        "eofa_inv_sqrt_rational", "eofa_schedule_candidates",
                         "eofa_apply", "eofa_apply_static", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
                         "eofa_kernel_timing", "eofa_cg_block", "eofa_graph_stats", "eofa_set_precond",
@@ -379,6 +380,15 @@ class Context:
         """Set the hop schedule (7 ints, as autotune returns them) for storage prec."""
         arr = (C.c_int * 7)(*[int(v) for v in sched])
         self._check(self.lib.eofa_set_schedule(self.h, int(prec), arr), "set_schedule")
+
+    def schedule_candidates(self, prec=FP64):
+        """The schedules autotune times for this lattice and storage prec, in its order (lists of 7 ints)."""
+        n = C.c_int()
+        self._check(self.lib.eofa_schedule_candidates(self.h, int(prec), 0, None, C.byref(n)), "schedule_candidates")
+        rows = (C.c_int * (7 * max(n.value, 1)))()
+        self._check(self.lib.eofa_schedule_candidates(self.h, int(prec), n.value, rows, C.byref(n)),
+                    "schedule_candidates")
+        return [list(rows[7 * i:7 * i + 7]) for i in range(n.value)]
 
     def autotune(self, prec=FP64, nrep=4, cache=None):
         """Pick the hop schedule for this lattice; cache: JSON path keyed by (dims, Ns, prec, arch)."""

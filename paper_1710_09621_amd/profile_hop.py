@@ -1,8 +1,10 @@
 """Profiling driver for the fused even-odd hop (run it under rocprofv3).
 
     python -m paper_1710_09621_amd.profile_hop [--dims 32 32 32 64] [--Ns 16] [--nrep 10] [--sched 1,1,4,4,8,32,0 ...]
+                                               [--all]
 
-Sets up the seeded lattice, autotunes the hop schedule (or takes the given ones, one after the other),
+Sets up the seeded lattice, autotunes the hop schedule (or takes the given ones, or with --all every schedule the
+autotuner would time, one after the other),
 launches the FP64 hop nrep times per schedule
 (the kernel behind the bench's dslash figure) and then applies the site-local A_T^{-1}
 (k_site: one streaming read and one streaming write of a half field per parity, the same
@@ -30,6 +32,7 @@ def main():
     ap.add_argument("--prec", type=int, default=0)
     ap.add_argument("--sched", action="append", default=[],
                     help="fixed schedule (7 comma-separated ints); repeat to time several in one process")
+    ap.add_argument("--all", action="store_true", help="every candidate schedule of the autotuner, in its order")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -39,22 +42,20 @@ def main():
     U = IN.gauge_links(dims, args.eps, 5)
     ctx = E.Context(dims, args.Ns, IN.M0, IN.optimal_omega(args.Ns))
     ctx.set_gauge(U)
-    runs = []
-    if args.sched:
-        for sc in args.sched:
-            sched = [int(v) for v in sc.split(",")]
-            ctx.set_schedule(sched, prec=args.prec)
-            runs.append((sched, ctx.dslash_bench(nrep=args.nrep, prec=args.prec)))
-    else:
-        tune = ctx.autotune(prec=args.prec)
-        runs.append((tune["sched"], ctx.dslash_bench(nrep=args.nrep, prec=args.prec)))
+    scheds = [[int(v) for v in sc.split(",")] for sc in args.sched]
+    if args.all:
+        scheds += ctx.schedule_candidates(prec=args.prec)
+    if not scheds:
+        scheds = [ctx.autotune(prec=args.prec)["sched"]]
+    Vh = int(np.prod(dims)) // 2
+    for sched in scheds:
+        ctx.set_schedule(sched, prec=args.prec)
+        r = ctx.dslash_bench(nrep=args.nrep, prec=args.prec)
+        print(json.dumps(dict(dims=dims, Ns=args.Ns, prec=args.prec, schedule=sched, ms=r["ms"], gbs=r["gbs"],
+                              alg_bytes=r["bytes"], site_kernel_bytes_each_way=Vh * 12 * args.Ns * 16)), flush=True)
     x = torch.randn(ctx.shape5, dtype=torch.complex128, device="cuda")
     ctx.apply("AT_INV", x, 0.01, 0.01)
     torch.cuda.synchronize()
-    Vh = int(np.prod(dims)) // 2
-    for sched, r in runs:
-        print(json.dumps(dict(dims=dims, Ns=args.Ns, prec=args.prec, schedule=sched, ms=r["ms"], gbs=r["gbs"],
-                              alg_bytes=r["bytes"], site_kernel_bytes_each_way=Vh * 12 * args.Ns * 16)), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for profiles/ (run on the host after a profiled run).
 
     python -m paper_1710_09621_amd.profile_summary trace  DIR BENCH_JSON OUT_MD  "COMMAND"
-    python -m paper_1710_09621_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT_JSON "FETCH_COMMAND" "WRITE_COMMAND"
+    python -m paper_1710_09621_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT_JSON "FETCH_COMMAND" "WRITE_COMMAND" \
+        [FETCH_STDOUT]
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
 dominant kernel (the FP64 hop K1 of the schedule the bench picked), the average duration of its launches in
@@ -10,7 +11,9 @@ the timed steps next to the bench's own HIP-event figure.
 traffic: HBM bytes per launch of the FP64 hop under each profiled schedule from two `rocprofv3 --pmc` passes
 of profile_hop.py (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
 for k_site, which reads and writes exactly one FP64 half field; the result carries a hash of the kernel
-sources so that bench.py drops it once the kernels change.
+sources so that bench.py drops it once the kernels change.  The schedules, in launch order, come from the
+JSON lines profile_hop.py printed in the FETCH_SIZE run (FETCH_STDOUT), else from the --sched options of
+FETCH_COMMAND.
 """
 from __future__ import annotations
 
@@ -117,9 +120,14 @@ def _per_dispatch(d, counter):
     return [tuple(out[k]) for k in sorted(out)]
 
 
-def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, dims=(32, 32, 32, 64), Ns=16, nrep=3):
+def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, fetch_stdout=None, dims=(32, 32, 32, 64), Ns=16,
+            nrep=3):
     import re
-    scheds = [s.split()[0] for s in re.findall(r"--sched (\S+)", fetch_cmd)]
+    if fetch_stdout:
+        with open(fetch_stdout) as fo:
+            scheds = [",".join(map(str, json.loads(ln)["schedule"])) for ln in fo if ln.startswith("{")]
+    else:
+        scheds = [s.split()[0] for s in re.findall(r"--sched (\S+)", fetch_cmd)]
     f = _per_dispatch(fetch_dir, "FETCH_SIZE")
     w = _per_dispatch(write_dir, "WRITE_SIZE")
     Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
@@ -129,17 +137,19 @@ def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, dims=(32, 32, 
     ff = half / (sum(cal_f) / len(cal_f) * 1024)
     wf = half / (sum(cal_w) / len(cal_w) * 1024)
     alg = Vh * (2 * 12 * Ns * 16 + 8 * 9 * 16)
-    res = {"kernel": "FP64 fused hop with the A_T^-1 epilogue (k_hop / k_hop_tw <16, false, HM_SITE, false, double>)",
+    res = {"kernel": "FP64 fused hop with the A_T^-1 epilogue (k_hop / k_hop_tw / k_hop_tws <16, false, HM_SITE, false, double>)",
            "lattice": "x".join(map(str, dims)), "Ns": Ns, "commands": [fetch_cmd, write_cmd],
            "calibration": {"kernel": f"k_site<16, false, double> (reads and writes one FP64 half field, {half} bytes "
                                      "each way)", "fetch_kib": cal_f, "write_kib": cal_w,
                            "fetch_factor": round(ff, 4), "write_factor": round(wf, 4)},
+           "kernels": "schedule mode 0/1: k_hop, 3: k_hop_tw, 5: k_hop_tw with the x neighbours from LDS, 6: k_hop_tws",
            "algorithmic_bytes_per_launch": alg, "by_schedule": {}, "source_sha1": source_sha1(),
            "source_files": KERNEL_SOURCES}
 
     def hops(rows):
         return [v for nm, v in rows if re.search(r"k_hop(_tws?)?<16, false, 1, false, double", nm)]
     hf, hw = hops(f), hops(w)
+    assert len(hf) == len(hw) == len(scheds) * (nrep + 2), (len(hf), len(hw), len(scheds))
     # profile_hop.py: per schedule, 2 untimed + nrep timed launches; keep the nrep timed ones
     per = nrep + 2
     for i, s in enumerate(scheds):
@@ -147,12 +157,17 @@ def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, dims=(32, 32, 
         wk = hw[i * per + 2:(i + 1) * per]
         rd = ff * 1024 * sum(fk) / len(fk)
         wr = wf * 1024 * sum(wk) / len(wk)
-        res["by_schedule"][s] = {"kernel": {"3": "k_hop_tw", "5": "k_hop_tw", "6": "k_hop_tws"}.get(s.split(",")[0], "k_hop"),
-                                 "fetch_kib_per_launch": fk, "write_kib_per_launch": wk,
-                                 "read_bytes_per_launch": round(rd), "write_bytes_per_launch": round(wr),
-                                 "bytes_per_launch": round(rd + wr), "amplification": round((rd + wr) / alg, 4)}
+        # one row per candidate of the autotuner (fields as in by_schedule_fields)
+        res["by_schedule"][s] = [round(rd), round(wr), round(rd + wr), round((rd + wr) / alg, 4)]
+    res["by_schedule_fields"] = ["read_bytes_per_launch", "write_bytes_per_launch", "bytes_per_launch",
+                                 "amplification"]
+    rows = res.pop("by_schedule")
+    text = json.dumps(res, indent=1)[:-2]
+    text += ',\n "by_schedule": {\n' + ",\n".join(f'  "{k}": {json.dumps(v)}' for k, v in rows.items()) + "\n }\n}\n"
+    json.loads(text)
     with open(out_json, "w") as fo:
-        json.dump(res, fo, indent=1)
+        fo.write(text)
+    res["by_schedule"] = {k: {"amplification": v[3]} for k, v in rows.items()}
     print(out_json, {k: v["amplification"] for k, v in res["by_schedule"].items()})
 
 
@@ -160,6 +175,6 @@ if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:6])
     elif sys.argv[1] == "traffic":
-        traffic(*sys.argv[2:7])
+        traffic(*sys.argv[2:8])
     else:
         raise SystemExit(__doc__)

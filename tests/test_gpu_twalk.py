@@ -11,8 +11,9 @@ from gpu_common import ctx_and_oracle, rand5, relerr
 pytestmark = pytest.mark.gpu
 
 # lattices on which t-walk schedules exist (a t-slab holds a whole number of 256-lane segments);
-# several chunks of 16 slabs, Ns = 8, 16 (DPP lane exchange), 32 (ds_bpermute)
-CASES = [((8, 8, 8, 32), 16), ((8, 8, 8, 32), 8), ((16, 8, 4, 16), 32)]
+# several chunks of 16 slabs, Ns = 8, 16 (DPP lane exchange), 32 (ds_bpermute); (32, 4, 4, 16) at Ns = 16 has
+# the benchmark's x-line length (16 sites per parity, one line per segment)
+CASES = [((8, 8, 8, 32), 16), ((8, 8, 8, 32), 8), ((16, 8, 4, 16), 32), ((32, 4, 4, 16), 16)]
 OPS = ["DW", "HOP", "DT", "DT_DAG", "HT", "AT_INV", "SCHUR", "SCHUR_DAG", "SCHUR_NORMAL"]
 
 
@@ -53,6 +54,24 @@ def setup(request):
 def test_schedules_exist(setup):
     _, _, dims, Ns = setup
     assert len(tw_schedules(dims, Ns)) >= 4
+
+
+def test_candidate_list(setup):
+    """The library's list of autotuner candidates starts with the two linear orders, holds exactly the t-walk
+    schedules enumerated above for FP64 / FP32 and none for FP16 storage, and every entry installs."""
+    from paper_1710_09621_amd import eofa as E
+    ctx, _, dims, Ns = setup
+    for p in (E.FP64, E.MIXED_FP32, E.MIXED_FP16):
+        c = ctx.schedule_candidates(prec=p)
+        assert [s[:2] for s in c[:2]] == [[0, 0], [0, 1]]
+        tw = sorted(s for s in c if s[0] >= 3)
+        assert tw == (sorted(tw_schedules(dims, Ns)) if p != E.MIXED_FP16 else []), p
+        assert len({tuple(s) for s in c}) == len(c)
+        for s in c:
+            ctx.set_schedule(s, prec=p)
+        ctx.set_schedule(c[0], prec=p)
+    with pytest.raises(E.EofaError):
+        ctx.schedule_candidates(prec=7)
 
 
 @pytest.mark.parametrize("prec", ["FP64", "MIXED_FP32"])
