@@ -215,6 +215,60 @@ eofa_status eofa_heatbath(eofa_ctx *ctx, double m_lo, double m_hi, const void *e
  * on [lo, hi] with n <= 8 poles; *err = its max relative error on [lo, hi]. */
 eofa_status eofa_inv_sqrt_rational(double lo, double hi, int n, double *a0, double *a, double *b, double *err);
 
+/*
+ * HMC molecular dynamics (Sec. I; the integrator of Sec. III).  Phase space: the links U (canonical layout,
+ * periodic; the t boundary phase of the fermions is applied by the library) and the momenta
+ * P[mu][site][a] (8 real components of P = P^a T^a, T^a = lambda^a / 2, site in canonical order), with
+ *   H = 1/2 sum P^a P^a + S_g(U) + sum_i S_i(U),
+ *   S_g = beta sum_{x, mu < nu} (1 - Re Tr U_mu nu(x) / 3)   (the Wilson plaquette action of Sec. III),
+ * S_i = phi_i^dag A_i phi_i the chiral actions of an EOFA splitting (eofa_chiral_action), and the equations of
+ * motion dU/dtau = i P U, dP^a/dtau = -dH/dw^a (derivative along U -> exp(i w^a T^a) U).
+ */
+/* S_g of the links U (device, canonical). */
+eofa_status eofa_gauge_action(eofa_ctx *ctx, const void *U, double beta, double *S);
+/* force[mu][site][a] = dS_g/dw^a of the links U (device, canonical); force: device, 4 * V * 8 doubles. */
+eofa_status eofa_gauge_force(eofa_ctx *ctx, const void *U, double beta, double *force);
+
+/* One pseudofermion action of the molecular dynamics: the chiral action (chir; m3, m4, mo) of
+ * eofa_chiral_action on phi (4D canonical device buffer, held fixed during the trajectory), integrated on
+ * time-scale level `level` (1 .. nlevels - 1; level 0 is the gauge action). */
+typedef struct {
+    int chir;
+    double m3, m4, mo;
+    int level;
+    const void *phi;
+} eofa_md_action;
+typedef struct {
+    double beta;     /* plaquette coupling */
+    double tau;      /* trajectory length (Sec. III: 1) */
+    int nlevels;     /* time scales, 1 .. 4 */
+    int steps[4];    /* total integration steps of each level per trajectory, steps[j - 1] % (2 steps[j]) == 0;
+                        Sec. III uses (k0, k1, k2) = (480, 12, 6) */
+    double metropolis_u; /* in [0, 1): accept the trajectory if u < exp(-dH), else restore U; < 0: keep the end
+                            point without a test */
+} eofa_md_params;
+typedef struct {
+    double H0, H1, dH;           /* Hamiltonian at the start and the end of the trajectory */
+    double K0, K1, Sg0, Sg1, Sf0, Sf1;
+    int accepted;                /* 1 / 0 after a Metropolis test, -1 without one */
+    int force_evals[4];          /* momentum updates per level */
+    int link_updates;
+    long cg_iters;               /* CG iterations of every solve of the trajectory (forces and actions) */
+    double seconds;
+} eofa_md_info;
+/*
+ * One molecular-dynamics trajectory from (U, P): the second-order minimum-norm (Omelyan) integrator nested over
+ * time scales.  A step of level j, of size e = tau / steps[j], is
+ *   P -= lam e F_j;  X_{j-1}(e/2);  P -= (1 - 2 lam) e F_j;  X_{j-1}(e/2);  P -= lam e F_j,
+ * with lam = 0.1931833275037836, F_j the force of the actions of level j (F_0: the gauge force), X_{j-1}(h)
+ * steps[j-1] / (2 steps[j]) steps of level j - 1 over time h, and X_{-1}(h): U <- exp(i h P) U.
+ * U (device, canonical, in/out: the end point, or the start after a rejection) and P (device, in/out: the end
+ * momenta) are caller-owned; every solve uses `solve`.  The context's gauge field follows U.  EINVAL for bad
+ * levels, steps or arguments; a solve that does not converge stops the trajectory with its status.
+ */
+eofa_status eofa_md_trajectory(eofa_ctx *ctx, void *U, double *P, int nact, const eofa_md_action *acts,
+                               const eofa_md_params *md, const eofa_solve_params *solve, eofa_md_info *info);
+
 /* n systems H_T(m_plus[j], m_minus[j]) x5[j] = b5[j] solved together (the multi-RHS form of eofa_solve_ht; host
  * arrays of n device pointers to 5D canonical buffers, b5[j] != x5[j]).  Up to 8 systems share each launch
  * sequence, as in eofa_chiral_action_batch; info[j] per system (may be NULL). */

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeofa.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["kernels.hip", "cnn.hip", "force.hip", "sitetab.cpp", "eofa.cpp"]
+SOURCES = ["kernels.hip", "cnn.hip", "force.hip", "hmc.hip", "sitetab.cpp", "eofa.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

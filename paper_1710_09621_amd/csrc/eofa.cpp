@@ -25,6 +25,7 @@
 #include "../../include/eofa.h"
 #include "cnn.h"
 #include "force.h"
+#include "hmc.h"
 #include "eofa_int.h"
 
 using namespace eofa;
@@ -82,6 +83,8 @@ struct eofa_ctx {
     double* partials_mr = nullptr;
     int pstride = 0;
     std::map<std::tuple<int, double, double>, SiteOp*> tabs;
+    double* md_F = nullptr;  // molecular dynamics: one force field, 4 V 8 doubles
+    cd* md_U0 = nullptr;     // the links at the start of a trajectory (restored on rejection)
     void* hb = nullptr;  // heat-bath: the 4D outputs of the shifted chiral actions
     size_t hb_bytes = 0;
     std::string err;
@@ -1781,6 +1784,134 @@ std::vector<SiteKind> op_kinds(int op) {
     }
 }
 
+// Pack the canonical links U into the per-parity FP64 and FP32 hop layouts (stream-ordered, no sync).
+void pack_gauge(eofa_ctx* ctx, const cd* U) {
+    const size_t n = (size_t)ctx->g.Vh * 36;
+    for (int par = 0; par < 2; par++) {
+        if (!ctx->U[par]) HIPCHK(hipMalloc(&ctx->U[par], n * sizeof(cd)));
+        if (!ctx->Uf[par]) HIPCHK(hipMalloc(&ctx->Uf[par], n * sizeof(cpx<float>)));
+        HIPCHK(launch_pack_links<double>(U, ctx->U[par], ctx->g, par, (double)ctx->tbc, ctx->st));
+        HIPCHK(launch_pack_links<float>(U, ctx->Uf[par], ctx->g, par, (double)ctx->tbc, ctx->st));
+    }
+    ctx->gauge = true;
+}
+
+// Solve and force of one chiral action into force[mu][site][8] (both parities' links).
+eofa_status chiral_force_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi,
+                              double* force, double* S, const eofa_solve_params* params, eofa_solve_info* info) {
+    check_params(ctx, params);
+    REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
+    ensure_ws(ctx, needed_bytes(ctx, params));
+    Work64 W = carve64(ctx);
+    // the 4D output of the action is not needed: a workspace field (written after the solve) takes it
+    eofa_status st = chiral_impl(ctx, chir, m3, m4, mo, phi, (void*)W.res.h[0], 0, S, params, info);
+    if (st != EOFA_OK && st != EOFA_ENOCONV) return st;
+    const double kappa = chir * action_k(chir, m3, m4, mo);
+    for (int par = 0; par < 2; par++)
+        HIPCHK(launch_force(W.x.h[par], W.x.h[1 - par], ctx->U[par], ctx->g, par, ctx->Ns, kappa, force, ctx->st));
+    return st;
+}
+
+// Doubles of a momentum or force field: 4 directions x V sites x 8 components (V = 2 Vh).
+size_t md_len(const eofa_ctx* ctx) { return 4 * 8 * 2 * (size_t)ctx->g.Vh; }
+
+// S_g = beta sum (1 - Re Tr U_P / 3) of the canonical links U.
+double gauge_action_dev(eofa_ctx* ctx, const cd* U, double beta) {
+    const Red red = red_of(ctx, SC_TMP + 17, EPI_STORE);
+    HIPCHK(launch_plaquette(U, ctx->g, red, ctx->st));
+    HIPCHK(launch_finish(red, (unsigned)((2 * (size_t)ctx->g.Vh + 255) / 256), ctx->st));
+    sync_scal(ctx);
+    return beta * ctx->hscal[SC_TMP + 17];
+}
+
+// 1/2 sum P^a P^a over the 32 V momentum components.
+double kinetic_dev(eofa_ctx* ctx, const double* P) {
+    HIPCHK(launch_norm2<double>((const cd*)P, md_len(ctx) / 2, red_of(ctx, SC_TMP + 18, EPI_STORE), ctx->st));
+    sync_scal(ctx);
+    return 0.5 * ctx->hscal[SC_TMP + 18];
+}
+
+// The nested Omelyan integration of the molecular dynamics (see eofa_md_trajectory).
+struct MdRun {
+    eofa_ctx* ctx;
+    cd* U;
+    double* P;
+    int nact;
+    const eofa_md_action* acts;
+    const eofa_md_params* md;
+    const eofa_solve_params* sp;
+    eofa_md_info* info;
+    eofa_status st = EOFA_OK;
+};
+
+constexpr double kOmelyanLambda = 0.1931833275037836;
+
+void md_kick(MdRun& m, int level, double h) {
+    eofa_ctx* ctx = m.ctx;
+    m.info->force_evals[level]++;
+    if (level == 0) {
+        HIPCHK(launch_gauge_force(m.U, ctx->g, m.md->beta, nullptr, m.P, h, 1, ctx->st));
+        return;
+    }
+    for (int i = 0; i < m.nact; i++) {
+        const eofa_md_action& a = m.acts[i];
+        if (a.level != level) continue;
+        eofa_solve_info si{};
+        const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, nullptr, m.sp, &si);
+        m.info->cg_iters += si.iters;
+        if (st != EOFA_OK) {
+            m.st = st;
+            throw Fail{st};
+        }
+        HIPCHK(launch_kick(m.P, ctx->md_F, h, md_len(ctx), ctx->st));
+    }
+}
+
+void md_links(MdRun& m, double h) {
+    eofa_ctx* ctx = m.ctx;
+    HIPCHK(launch_link_update(m.U, m.P, h, ctx->g, ctx->st));
+    pack_gauge(ctx, m.U);
+    m.info->link_updates++;
+}
+
+void md_integrate(MdRun& m, int level, double tau) {
+    const int top = m.md->nlevels - 1;
+    const int n = level == top ? m.md->steps[level] : m.md->steps[level] / (2 * m.md->steps[level + 1]);
+    const double e = tau / n, lam = kOmelyanLambda;
+    auto inner = [&](double h) {
+        if (level == 0) md_links(m, h);
+        else md_integrate(m, level - 1, h);
+    };
+    for (int k = 0; k < n; k++) {
+        md_kick(m, level, lam * e);
+        inner(e / 2);
+        md_kick(m, level, (1 - 2 * lam) * e);
+        inner(e / 2);
+        md_kick(m, level, lam * e);
+    }
+}
+
+// S_f = sum of the chiral actions at the current links; adds the solves' iterations to info.
+double fermion_action_dev(MdRun& m) {
+    eofa_ctx* ctx = m.ctx;
+    double sum = 0;
+    for (int i = 0; i < m.nact; i++) {
+        const eofa_md_action& a = m.acts[i];
+        ensure_ws(ctx, needed_bytes(ctx, m.sp));
+        Work64 W = carve64(ctx);
+        double S = 0;
+        eofa_solve_info si{};
+        const eofa_status st = chiral_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, (void*)W.res.h[0], 0, &S, m.sp, &si);
+        m.info->cg_iters += si.iters;
+        if (st != EOFA_OK) {
+            m.st = st;
+            throw Fail{st};
+        }
+        sum += S;
+    }
+    return sum;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -1862,15 +1993,8 @@ eofa_status eofa_set_workspace(eofa_ctx* ctx, void* dev_ptr, size_t bytes) {
 eofa_status eofa_set_gauge(eofa_ctx* ctx, const void* U) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(U != nullptr, EOFA_EINVAL, "U is NULL");
-        const size_t n = (size_t)ctx->g.Vh * 36;
-        for (int par = 0; par < 2; par++) {
-            if (!ctx->U[par]) HIPCHK(hipMalloc(&ctx->U[par], n * sizeof(cd)));
-            if (!ctx->Uf[par]) HIPCHK(hipMalloc(&ctx->Uf[par], n * sizeof(cpx<float>)));
-            HIPCHK(launch_pack_links<double>((const cd*)U, ctx->U[par], ctx->g, par, (double)ctx->tbc, ctx->st));
-            HIPCHK(launch_pack_links<float>((const cd*)U, ctx->Uf[par], ctx->g, par, (double)ctx->tbc, ctx->st));
-        }
+        pack_gauge(ctx, (const cd*)U);
         HIPCHK(hipStreamSynchronize(ctx->st));
-        ctx->gauge = true;
         return EOFA_OK;
     });
 }
@@ -1884,18 +2008,77 @@ eofa_status eofa_chiral_force(eofa_ctx* ctx, int chir, double m3, double m4, dou
                               double* S, const eofa_solve_params* params, eofa_solve_info* info) {
     return guarded(ctx, [&]() -> eofa_status {
         REQUIRE(force, EOFA_EINVAL, "null force pointer");
-        check_params(ctx, params);
-        REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
-        ensure_ws(ctx, needed_bytes(ctx, params));
-        Work64 W = carve64(ctx);
-        // the 4D output of the action is not needed: a workspace field (written after the solve) takes it
-        eofa_status st = chiral_impl(ctx, chir, m3, m4, mo, phi, (void*)W.res.h[0], 0, S, params, info);
-        if (st != EOFA_OK && st != EOFA_ENOCONV) return st;
-        const double kappa = chir * action_k(chir, m3, m4, mo);
-        for (int par = 0; par < 2; par++)
-            HIPCHK(launch_force(W.x.h[par], W.x.h[1 - par], ctx->U[par], ctx->g, par, ctx->Ns, kappa, force, ctx->st));
+        const eofa_status st = chiral_force_impl(ctx, chir, m3, m4, mo, phi, force, S, params, info);
         HIPCHK(hipStreamSynchronize(ctx->st));
         return st;
+    });
+}
+
+eofa_status eofa_gauge_action(eofa_ctx* ctx, const void* U, double beta, double* S) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(U && S, EOFA_EINVAL, "null pointer");
+        *S = gauge_action_dev(ctx, (const cd*)U, beta);
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_gauge_force(eofa_ctx* ctx, const void* U, double beta, double* force) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(U && force, EOFA_EINVAL, "null pointer");
+        HIPCHK(launch_gauge_force((const cd*)U, ctx->g, beta, force, nullptr, 0.0, 0, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        return EOFA_OK;
+    });
+}
+
+eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, const eofa_md_action* acts,
+                               const eofa_md_params* md, const eofa_solve_params* solve, eofa_md_info* info) {
+    return guarded(ctx, [&]() -> eofa_status {
+        REQUIRE(U && P && md && solve && info, EOFA_EINVAL, "null pointer");
+        REQUIRE(nact >= 0 && (nact == 0 || acts), EOFA_EINVAL, "bad action list");
+        REQUIRE(md->nlevels >= 1 && md->nlevels <= 4, EOFA_EINVAL, "nlevels must be 1 .. 4");
+        REQUIRE(md->tau > 0 && std::isfinite(md->tau) && std::isfinite(md->beta), EOFA_EINVAL, "bad tau or beta");
+        REQUIRE(md->metropolis_u < 1.0, EOFA_EINVAL, "metropolis_u must be < 1");
+        for (int j = 0; j < md->nlevels; j++) REQUIRE(md->steps[j] >= 1, EOFA_EINVAL, "steps must be >= 1");
+        for (int j = 1; j < md->nlevels; j++)
+            REQUIRE(md->steps[j - 1] % (2 * md->steps[j]) == 0, EOFA_EINVAL,
+                    "steps[j - 1] must be a multiple of 2 steps[j]");
+        // every link update is a kernel plus a repack: bound the work of one call
+        REQUIRE((long)md->steps[0] <= 100000, EOFA_EINVAL, "too many steps");
+        for (int i = 0; i < nact; i++) {
+            REQUIRE(acts[i].level >= 1 && acts[i].level < md->nlevels, EOFA_EINVAL, "action level out of range");
+            REQUIRE(acts[i].phi, EOFA_EINVAL, "null phi");
+        }
+        check_params(ctx, solve);
+        const auto t0 = std::chrono::steady_clock::now();
+        *info = eofa_md_info{};
+        info->accepted = -1;
+        const size_t nU = 72 * (size_t)ctx->g.Vh;  // complex entries of the canonical links
+        if (!ctx->md_F) HIPCHK(hipMalloc(&ctx->md_F, sizeof(double) * md_len(ctx)));
+        if (md->metropolis_u >= 0 && !ctx->md_U0) HIPCHK(hipMalloc(&ctx->md_U0, sizeof(cd) * nU));
+        MdRun m{ctx, (cd*)U, P, nact, acts, md, solve, info};
+        if (md->metropolis_u >= 0) HIPCHK(launch_copy(ctx->md_U0, U, sizeof(cd) * nU, ctx->st));
+        pack_gauge(ctx, (const cd*)U);
+        info->K0 = kinetic_dev(ctx, P);
+        info->Sg0 = gauge_action_dev(ctx, (const cd*)U, md->beta);
+        info->Sf0 = fermion_action_dev(m);
+        md_integrate(m, md->nlevels - 1, md->tau);
+        info->K1 = kinetic_dev(ctx, P);
+        info->Sg1 = gauge_action_dev(ctx, (const cd*)U, md->beta);
+        info->Sf1 = fermion_action_dev(m);
+        info->H0 = info->K0 + info->Sg0 + info->Sf0;
+        info->H1 = info->K1 + info->Sg1 + info->Sf1;
+        info->dH = info->H1 - info->H0;
+        if (md->metropolis_u >= 0) {
+            info->accepted = (md->metropolis_u < std::exp(-info->dH)) ? 1 : 0;
+            if (!info->accepted) {
+                HIPCHK(launch_copy(U, ctx->md_U0, sizeof(cd) * nU, ctx->st));
+                pack_gauge(ctx, (const cd*)U);
+            }
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return EOFA_OK;
     });
 }
 
@@ -2406,6 +2589,8 @@ void eofa_destroy(eofa_ctx* ctx) {
     if (ctx->ws && ctx->ws_owned) (void)hipFree(ctx->ws);
     if (ctx->partials) (void)hipFree(ctx->partials);
     if (ctx->hb) (void)hipFree(ctx->hb);
+    if (ctx->md_F) (void)hipFree(ctx->md_F);
+    if (ctx->md_U0) (void)hipFree(ctx->md_U0);
     if (ctx->partials_mr) (void)hipFree(ctx->partials_mr);
     {
         auto& c = ctx->cnn;

@@ -65,6 +65,28 @@ class SolveInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class MdAction(C.Structure):
+    _fields_ = [("chir", C.c_int), ("m3", C.c_double), ("m4", C.c_double), ("mo", C.c_double), ("level", C.c_int),
+                ("phi", C.c_void_p)]
+
+
+class MdParams(C.Structure):
+    _fields_ = [("beta", C.c_double), ("tau", C.c_double), ("nlevels", C.c_int), ("steps", C.c_int * 4),
+                ("metropolis_u", C.c_double)]
+
+
+class MdInfo(C.Structure):
+    _fields_ = [("H0", C.c_double), ("H1", C.c_double), ("dH", C.c_double), ("K0", C.c_double),
+                ("K1", C.c_double), ("Sg0", C.c_double), ("Sg1", C.c_double), ("Sf0", C.c_double),
+                ("Sf1", C.c_double), ("accepted", C.c_int), ("force_evals", C.c_int * 4), ("link_updates", C.c_int),
+                ("cg_iters", C.c_long), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["force_evals"] = list(self.force_evals)
+        return d
+
+
 def params(tol=1e-10, max_iter=100000, prec=FP64, pc=PC_NONE, reliable_delta=0.0, use_graph=0, check_every=0):
     return SolveParams(tol, max_iter, prec, pc, reliable_delta, use_graph, check_every)
 
@@ -116,6 +138,10 @@ def load():
         "eofa_autotune": [P, I, I, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "eofa_set_schedule": [P, I, C.POINTER(C.c_int)],
         "eofa_schedule_candidates": [P, I, I, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+        "eofa_gauge_action": [P, P, D, C.POINTER(C.c_double)],
+        "eofa_gauge_force": [P, P, D, P],
+        "eofa_md_trajectory": [P, P, P, I, C.POINTER(MdAction), C.POINTER(MdParams), C.POINTER(SolveParams),
+                               C.POINTER(MdInfo)],
         "eofa_last_error": [P],
         "eofa_destroy": [P],
     }
@@ -135,6 +161,7 @@ def exported_symbols():
     return [n for n in ("eofa_create", "eofa_workspace_size", "eofa_set_workspace", "eofa_set_gauge", "eofa_hinv",
                         "eofa_chiral_action", "eofa_chiral_force", "eofa_chiral_action_batch", "eofa_hinv_batch", "eofa_solve_ht", "eofa_solve_ht_batch", "eofa_chiral_heatbath", "eofa_heatbath",
                         "eofa_inv_sqrt_rational", "eofa_schedule_candidates",
+                        "eofa_gauge_action", "eofa_gauge_force", "eofa_md_trajectory",
                         "eofa_apply", "eofa_apply_static", "eofa_dslash_bench", "eofa_autotune", "eofa_set_schedule", "eofa_cnn_init",
                         "eofa_cnn_params", "eofa_cnn_apply", "eofa_cnn_train_step", "eofa_training_pairs",
                         "eofa_kernel_timing", "eofa_cg_block", "eofa_graph_stats", "eofa_set_precond",
@@ -339,6 +366,50 @@ class Context:
                                         C.byref(S), C.byref(p), C.byref(info))
         self._check(st, "chiral_force")
         return F, S.value, info.as_dict()
+
+    def _links(self, U):
+        Lx, Ly, Lz, Lt = self.dims
+        return self._c128(U, (Lt, Lz, Ly, Lx, 4, 3, 3))
+
+    def gauge_action(self, U, beta):
+        """Wilson plaquette action S_g of the canonical links U."""
+        U = self._links(U)
+        S = C.c_double()
+        self._check(self.lib.eofa_gauge_action(self.h, _ptr(U), float(beta), C.byref(S)), "gauge_action")
+        return S.value
+
+    def gauge_force(self, U, beta):
+        """F[mu][t][z][y][x][a] = dS_g/dw^a (float64 on the device)."""
+        U = self._links(U)
+        Lx, Ly, Lz, Lt = self.dims
+        F = self.torch.empty((4, Lt, Lz, Ly, Lx, 8), dtype=self.torch.float64, device=U.device)
+        self._check(self.lib.eofa_gauge_force(self.h, _ptr(U), float(beta), _ptr(F)), "gauge_force")
+        return F
+
+    def md_trajectory(self, U, P, actions, beta, tau, steps, metropolis_u=-1.0, p=None):
+        """One molecular-dynamics trajectory, in place on U (complex128 [t][z][y][x][mu][3][3]) and P (float64
+        [mu][t][z][y][x][8]), both device tensors.  actions: list of (level, chir, m3, m4, mo, phi); steps: total
+        steps per level, innermost (gauge) first.  Returns the info dict."""
+        torch = self.torch
+        Lx, Ly, Lz, Lt = self.dims
+        assert isinstance(U, torch.Tensor) and U.dtype == torch.complex128 and U.is_contiguous()
+        assert tuple(U.shape) == (Lt, Lz, Ly, Lx, 4, 3, 3) and U.device.type == "cuda"
+        assert isinstance(P, torch.Tensor) and P.dtype == torch.float64 and P.is_contiguous()
+        assert tuple(P.shape) == (4, Lt, Lz, Ly, Lx, 8) and P.device.type == "cuda"
+        p = p or params()
+        phis = [self._c128(a[5], self.shape4) for a in actions]
+        acts = (MdAction * max(1, len(actions)))()
+        for i, (lev, chir, m3, m4, mo, _) in enumerate(actions):
+            acts[i] = MdAction(int(chir), float(m3), float(m4), float(mo), int(lev), phis[i].data_ptr())
+        steps = list(steps)
+        md = MdParams(float(beta), float(tau), len(steps), (C.c_int * 4)(*(steps + [0] * (4 - len(steps)))),
+                      float(metropolis_u))
+        self._prep_ws(p)
+        info = MdInfo()
+        st = self.lib.eofa_md_trajectory(self.h, _ptr(U), _ptr(P), len(actions), acts, C.byref(md), C.byref(p),
+                                         C.byref(info))
+        self._check(st, "md_trajectory")
+        return info.as_dict()
 
     def hinv(self, phi, m_lo, m_hi, p=None):
         p = p or params()

@@ -1,0 +1,108 @@
+"""HMC of one-flavour QCD with the exact one-flavor action and mass preconditioning (Sec. I; Sec. III).
+
+    python -m paper_1710_09621_amd.hmc [--config 2] [--scheme new] [--ntraj 2] [--steps 480 12 6] [--beta 6.2]
+
+Every trajectory follows the outline of Sec. I:
+  (2) momenta P^a ~ N(0, 1) and (3) pseudofermion noise eta of weight exp(-eta^dag eta), drawn on the host from
+      seeded generators (the draws are inputs of the library);
+  (4) every pseudofermion field phi = A^{-1/2} P_c eta from the heat-bath of its chiral action
+      (eofa_chiral_heatbath);
+  (5) the molecular dynamics with the Omelyan integrator nested over three time scales and (6) the Metropolis
+      test, both in eofa_md_trajectory.
+The levels follow Sec. III: the gauge field at k0, the last (heaviest) factor of the splitting at k1, the other
+factors at k2, with (k0, k1, k2) = (480, 12, 6).  Prints one JSON line per trajectory and a summary.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def levels(acts):
+    """(level, chir, m3, m4, mo) per chiral action of a splitting: the last factor at level 1, the others at 2."""
+    return [(1 if i == len(acts) - 1 else 2,) + tuple(a) for i, a in enumerate(acts)]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--config", type=int, default=2, help="synthetic start field and lattice (inputs.CONFIGS)")
+    ap.add_argument("--dims", type=int, nargs=4, default=None)
+    ap.add_argument("--Ns", type=int, default=None)
+    ap.add_argument("--scheme", choices=("none", "old", "new"), default="new")
+    ap.add_argument("--m", type=float, default=0.01)
+    ap.add_argument("--mh", type=float, default=0.1)
+    ap.add_argument("--M", type=float, default=1.0)
+    ap.add_argument("--beta", type=float, default=6.2)
+    ap.add_argument("--tau", type=float, default=1.0)
+    ap.add_argument("--steps", type=int, nargs=3, default=[480, 12, 6])
+    ap.add_argument("--ntraj", type=int, default=2)
+    ap.add_argument("--prec", choices=("fp64", "fp16"), default="fp16")
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--out", default=None, help="also write the lines to this file")
+    args = ap.parse_args()
+
+    import numpy as np
+    import torch
+    from paper_1710_09621_amd import eofa as E
+    from paper_1710_09621_amd import inputs as IN
+    from paper_1710_09621_amd import mpseq
+
+    cfg = IN.CONFIGS[args.config]
+    dims = tuple(args.dims or cfg["dims"])
+    Ns = args.Ns or cfg["Ns"]
+    Lx, Ly, Lz, Lt = dims
+    U = torch.from_numpy(IN.gauge_links(dims, cfg["eps"], cfg["seed"]).reshape(Lt, Lz, Ly, Lx, 4, 3, 3)).cuda()
+    ctx = E.Context(dims, Ns, IN.M0, IN.optimal_omega(Ns))
+    ctx.set_gauge(U)
+    prec = {"fp64": E.FP64, "fp16": E.MIXED_FP16}[args.prec]
+    p = E.params(tol=1e-10, prec=prec, max_iter=50000)
+    heavies = [] if args.scheme == "none" else [args.mh]
+    acts = levels(mpseq.actions(args.scheme, args.m, heavies, args.M))
+    rng = np.random.Generator(np.random.PCG64(args.seed))
+    lines = []
+    for traj in range(args.ntraj):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = torch.from_numpy(rng.standard_normal((4, Lt, Lz, Ly, Lx, 8))).cuda()
+        phis, hb = [], []
+        for (lev, chir, m3, m4, mo) in acts:
+            eta = (rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)) + 1j * rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)))
+            eta *= np.sqrt(0.5)
+            phi, info = ctx.chiral_heatbath(chir, m3, m4, mo, eta, p=p)
+            phis.append(phi)
+            hb.append(info)
+        torch.cuda.synchronize()
+        t_hb = time.perf_counter() - t0
+        u = float(rng.random())
+        md = ctx.md_trajectory(U, P, [a + (phis[i],) for i, a in enumerate(acts)], args.beta, args.tau,
+                               args.steps, metropolis_u=u, p=p)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        plaq = 1.0 - ctx.gauge_action(U, 1.0) / (6 * Lx * Ly * Lz * Lt)
+        line = dict(traj=traj, dH=md["dH"], accepted=md["accepted"], u=u, plaquette=plaq, seconds=round(t, 3),
+                    heatbath_s=round(t_hb, 3), md_s=round(md["seconds"], 3), cg_iters=md["cg_iters"],
+                    force_evals=md["force_evals"][:3], link_updates=md["link_updates"],
+                    hb_poles=[h["npoles"] for h in hb], H0=md["H0"], Sg0=md["Sg0"], Sf0=md["Sf0"])
+        lines.append(line)
+        print(json.dumps(line), flush=True)
+    summary = dict(lattice="x".join(map(str, dims)), Ns=Ns, scheme=args.scheme, actions=[list(a) for a in acts],
+                   beta=args.beta, steps=args.steps, prec=args.prec, ntraj=args.ntraj,
+                   accepted=sum(1 for x in lines if x["accepted"] == 1),
+                   mean_s=round(sum(x["seconds"] for x in lines) / len(lines), 3),
+                   mean_cg=round(sum(x["cg_iters"] for x in lines) / len(lines), 1))
+    print(json.dumps(dict(summary=summary)), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            for x in lines + [dict(summary=summary)]:
+                f.write(json.dumps(x) + "\n")
+
+
+if __name__ == "__main__":
+    main()
