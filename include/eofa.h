@@ -251,7 +251,7 @@ typedef struct {
     double H0, H1, dH;           /* Hamiltonian at the start and the end of the trajectory */
     double K0, K1, Sg0, Sg1, Sf0, Sf1;
     int accepted;                /* 1 / 0 after a Metropolis test, -1 without one */
-    int force_evals[4];          /* momentum updates per level */
+    int force_evals[4];          /* force evaluations per level: 2 steps[j] + 1 */
     int link_updates;
     long cg_iters;               /* CG iterations of every solve of the trajectory (forces and actions) */
     double seconds;
@@ -261,7 +261,10 @@ typedef struct {
  * time scales.  A step of level j, of size e = tau / steps[j], is
  *   P -= lam e F_j;  X_{j-1}(e/2);  P -= (1 - 2 lam) e F_j;  X_{j-1}(e/2);  P -= lam e F_j,
  * with lam = 0.1931833275037836, F_j the force of the actions of level j (F_0: the gauge force), X_{j-1}(h)
- * steps[j-1] / (2 steps[j]) steps of level j - 1 over time h, and X_{-1}(h): U <- exp(i h P) U.
+ * steps[j-1] / (2 steps[j]) steps of level j - 1 over time h, and X_{-1}(h): U <- exp(i h P) U.  Kicks of one
+ * level with no link update between them see the same links and share one force evaluation (2 steps[j] + 1 per
+ * level, the counts of Sec. III); the fermion actions in H at both ends come from the solves of the first and
+ * last force evaluations.
  * U (device, canonical, in/out: the end point, or the start after a rejection) and P (device, in/out: the end
  * momenta) are caller-owned; every solve uses `solve`.  The context's gauge field follows U.  EINVAL for bad
  * levels, steps or arguments; a solve that does not converge stops the trajectory with its status.

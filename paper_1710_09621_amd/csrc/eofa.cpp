@@ -1842,33 +1842,65 @@ struct MdRun {
     const eofa_solve_params* sp;
     eofa_md_info* info;
     eofa_status st = EOFA_OK;
+    // Momentum updates are deferred until the links change: the kicks of one level between two link updates
+    // see the same links, so their force is evaluated once with the summed step (pend[level]); kicks of
+    // different levels commute.  Every level has a pending kick at the start and at the end of the trajectory,
+    // so those two flushes also give every action's S (Sf_flush, with `all` set when each action was solved).
+    double pend[4] = {0, 0, 0, 0};
+    bool has[4] = {false, false, false, false};
+    double Sf_flush = 0;
+    bool all = false;
+    bool sf0 = false;  // info->Sf0 was taken from the first flush
 };
 
 constexpr double kOmelyanLambda = 0.1931833275037836;
 
 void md_kick(MdRun& m, int level, double h) {
+    m.pend[level] += h;
+    m.has[level] = true;
+}
+
+// Apply every pending kick at the current links.
+void md_flush(MdRun& m) {
     eofa_ctx* ctx = m.ctx;
-    m.info->force_evals[level]++;
-    if (level == 0) {
-        HIPCHK(launch_gauge_force(m.U, ctx->g, m.md->beta, nullptr, m.P, h, 1, ctx->st));
-        return;
-    }
-    for (int i = 0; i < m.nact; i++) {
-        const eofa_md_action& a = m.acts[i];
-        if (a.level != level) continue;
-        eofa_solve_info si{};
-        const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, nullptr, m.sp, &si);
-        m.info->cg_iters += si.iters;
-        if (st != EOFA_OK) {
-            m.st = st;
-            throw Fail{st};
+    m.Sf_flush = 0;
+    int solved = 0;
+    for (int level = 0; level < m.md->nlevels; level++) {
+        if (!m.has[level]) continue;
+        const double h = m.pend[level];
+        m.pend[level] = 0;
+        m.has[level] = false;
+        m.info->force_evals[level]++;
+        if (level == 0) {
+            HIPCHK(launch_gauge_force(m.U, ctx->g, m.md->beta, nullptr, m.P, h, 1, ctx->st));
+            continue;
         }
-        HIPCHK(launch_kick(m.P, ctx->md_F, h, md_len(ctx), ctx->st));
+        for (int i = 0; i < m.nact; i++) {
+            const eofa_md_action& a = m.acts[i];
+            if (a.level != level) continue;
+            eofa_solve_info si{};
+            double S = 0;
+            const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, &S, m.sp, &si);
+            m.info->cg_iters += si.iters;
+            if (st != EOFA_OK) {
+                m.st = st;
+                throw Fail{st};
+            }
+            m.Sf_flush += S;
+            solved++;
+            HIPCHK(launch_kick(m.P, ctx->md_F, h, md_len(ctx), ctx->st));
+        }
     }
+    m.all = (solved == m.nact);
 }
 
 void md_links(MdRun& m, double h) {
     eofa_ctx* ctx = m.ctx;
+    md_flush(m);
+    if (m.info->link_updates == 0 && m.all) {  // the first flush: every action at U(0)
+        m.info->Sf0 = m.Sf_flush;
+        m.sf0 = true;
+    }
     HIPCHK(launch_link_update(m.U, m.P, h, ctx->g, ctx->st));
     pack_gauge(ctx, m.U);
     m.info->link_updates++;
@@ -1889,27 +1921,6 @@ void md_integrate(MdRun& m, int level, double tau) {
         inner(e / 2);
         md_kick(m, level, lam * e);
     }
-}
-
-// S_f = sum of the chiral actions at the current links; adds the solves' iterations to info.
-double fermion_action_dev(MdRun& m) {
-    eofa_ctx* ctx = m.ctx;
-    double sum = 0;
-    for (int i = 0; i < m.nact; i++) {
-        const eofa_md_action& a = m.acts[i];
-        ensure_ws(ctx, needed_bytes(ctx, m.sp));
-        Work64 W = carve64(ctx);
-        double S = 0;
-        eofa_solve_info si{};
-        const eofa_status st = chiral_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, (void*)W.res.h[0], 0, &S, m.sp, &si);
-        m.info->cg_iters += si.iters;
-        if (st != EOFA_OK) {
-            m.st = st;
-            throw Fail{st};
-        }
-        sum += S;
-    }
-    return sum;
 }
 
 }  // namespace
@@ -2061,11 +2072,14 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
         pack_gauge(ctx, (const cd*)U);
         info->K0 = kinetic_dev(ctx, P);
         info->Sg0 = gauge_action_dev(ctx, (const cd*)U, md->beta);
-        info->Sf0 = fermion_action_dev(m);
         md_integrate(m, md->nlevels - 1, md->tau);
+        md_flush(m);  // the last kicks, at U(tau)
+        // every level kicks before the first link update and after the last one, so both flushes solved every
+        // action; anything else is a defect of the integrator
+        REQUIRE(m.sf0 && m.all, EOFA_EHIP, "internal: the end flushes did not evaluate every action");
+        info->Sf1 = m.Sf_flush;
         info->K1 = kinetic_dev(ctx, P);
         info->Sg1 = gauge_action_dev(ctx, (const cd*)U, md->beta);
-        info->Sf1 = fermion_action_dev(m);
         info->H0 = info->K0 + info->Sg0 + info->Sf0;
         info->H1 = info->K1 + info->Sg1 + info->Sf1;
         info->dH = info->H1 - info->H0;

@@ -3,6 +3,7 @@
     python -m paper_1710_09621_amd.profile_summary trace  DIR BENCH_JSON OUT_MD  "COMMAND"
     python -m paper_1710_09621_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT_JSON "FETCH_COMMAND" "WRITE_COMMAND" \
         [FETCH_STDOUT]
+    python -m paper_1710_09621_amd.profile_summary hmc DIR RUN1.jsonl,RUN2.jsonl OUT_MD "TRACE_COMMAND" "RUN_COMMAND"
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
 dominant kernel (the FP64 hop K1 of the schedule the bench picked), the average duration of its launches in
@@ -171,10 +172,60 @@ def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, fetch_stdout=N
     print(out_json, {k: v["amplification"] for k, v in res["by_schedule"].items()})
 
 
+def hmc(d, runs, out_md, command, run_command):
+    """Kernel-time split of one HMC trajectory (rocprofv3 --stats of hmc.py) and the per-trajectory lines of the
+    three splittings (hmc.py --out files, comma-separated)."""
+    stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
+    total = sum(float(_col(r, "TotalDurationNs")) for r in stats)
+    groups = {"gauge force + kick": ("k_gauge_force",), "link update": ("k_link_update",),
+              "link packing": ("k_pack_links",), "fermion force": ("k_force<",),
+              "plaquette action": ("k_plaquette",)}
+    split = {k: 0.0 for k in groups}
+    split["solves (hops, CG updates and reductions, sources, heat-bath)"] = 0.0
+    for r in stats:
+        nm = _col(r, "Name", "KernelName", "Kernel_Name")
+        t = float(_col(r, "TotalDurationNs"))
+        for g, keys in groups.items():
+            if any(k in nm for k in keys):
+                split[g] += t
+                break
+        else:
+            split["solves (hops, CG updates and reductions, sources, heat-bath)"] += t
+    lines = ["# HMC trajectories of one-flavour EOFA on 16x16x16x32, Ns = 16", "",
+             "Trajectories (repository root, GPU box):", "", f"    {run_command}", "",
+             "| splitting | trajectory | dH | accepted | seconds | heat-bath s | MD s | CG iterations | force evaluations (k0, k1, k2) |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---|"]
+    for path in runs.split(","):
+        with open(path) as f:
+            rows = [json.loads(ln) for ln in f if ln.strip()]
+        summ = [r["summary"] for r in rows if "summary" in r][0]
+        for r in rows:
+            if "summary" in r:
+                continue
+            lines.append(f"| {summ['scheme']} ({len(summ['actions'])} actions) | {r['traj']} | {r['dH']:.3f} | "
+                         f"{r['accepted']} | {r['seconds']:.2f} | {r['heatbath_s']:.2f} | {r['md_s']:.2f} | "
+                         f"{r['cg_iters']} | {r['force_evals']} |")
+    lines += ["", "Kernel trace of one new-MP trajectory:", "", f"    {command}", "",
+              "| part | device time ms | share |", "|---|---:|---:|"]
+    for g, t in sorted(split.items(), key=lambda kv: -kv[1]):
+        lines.append(f"| {g} | {t / 1e6:.1f} | {100 * t / total:.1f}% |")
+    stats.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
+    lines += ["", "| kernel | calls | avg us | total % |", "|---|---:|---:|---:|"]
+    for r in stats[:12]:
+        nm = _col(r, "Name", "KernelName", "Kernel_Name").replace("|", "\\|")
+        lines.append(f"| `{nm[:100]}` | {_col(r, 'Calls')} | {float(_col(r, 'AverageNs')) / 1e3:.1f} | "
+                     f"{100 * float(_col(r, 'TotalDurationNs')) / total:.2f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out_md, {k: round(v / 1e6, 1) for k, v in split.items()})
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:6])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:8])
+    elif sys.argv[1] == "hmc":
+        hmc(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)
