@@ -246,6 +246,8 @@ typedef struct {
                         Sec. III uses (k0, k1, k2) = (480, 12, 6) */
     double metropolis_u; /* in [0, 1): accept the trajectory if u < exp(-dH), else restore U; < 0: keep the end
                             point without a test */
+    int chrono;          /* != 0: every force solve after an action's first in the trajectory starts from that
+                            action's previous solution (kept in 2 half fields per action, allocated once) */
 } eofa_md_params;
 typedef struct {
     double H0, H1, dH;           /* Hamiltonian at the start and the end of the trajectory */

@@ -85,6 +85,7 @@ struct eofa_ctx {
     std::map<std::tuple<int, double, double>, SiteOp*> tabs;
     double* md_F = nullptr;  // molecular dynamics: one force field, 4 V 8 doubles
     cd* md_U0 = nullptr;     // the links at the start of a trajectory (restored on rejection)
+    std::vector<cd*> md_guess;  // chronological start vectors, two halves per action
     void* hb = nullptr;  // heat-bath: the 4D outputs of the shifted chiral actions
     size_t hb_bytes = 0;
     std::string err;
@@ -883,7 +884,8 @@ CgOut eo_correct64(eofa_ctx* ctx, const Work64& W, double mp, double mm, double 
     return o;
 }
 
-SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P);
+SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P,
+                  bool guess = false);
 
 int auto_check_every(const eofa_solve_params& P) { return P.check_every > 0 ? P.check_every : kAutoCheckEvery; }
 
@@ -917,10 +919,19 @@ void refine(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_sol
     }
 }
 
-SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
+// guess: W.x holds a start vector (a previous solution); it is used when its residual is below |c|.
+SolveOut solve_dt_fp64(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P,
+                       bool guess = false) {
     SolveOut so;
     const double cn2 = norm2_64(ctx, W.c);
     REQUIRE(std::isfinite(cn2), EOFA_EINVAL, "source has non-finite entries");
+    if (guess && cn2 > 0.0) {
+        const double r2 = residual64(ctx, W, mp, mm);  // W.res = c - D_T x
+        if (std::isfinite(r2) && r2 < cn2) {
+            refine(ctx, W, mp, mm, P, cn2, std::sqrt(r2 / cn2), so);
+            return so;
+        }
+    }
     for (int par = 0; par < 2; par++) {
         HIPCHK(hipMemsetAsync(W.x.h[par], 0, ctx->nh * sizeof(cd), ctx->st));
         HIPCHK(hipMemcpyAsync(W.res.h[par], W.c.h[par], ctx->nh * sizeof(cd), hipMemcpyDeviceToDevice, ctx->st));
@@ -1152,14 +1163,14 @@ void check_params(eofa_ctx* ctx, const eofa_solve_params* P) {
     REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
 }
 
-SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P) {
+SolveOut solve_dt(eofa_ctx* ctx, const Work64& W, double mp, double mm, const eofa_solve_params& P, bool guess) {
     if (P.prec == EOFA_MIXED_FP16)
         REQUIRE(ctx->Ns >= 8 && ctx->Ns % 8 == 0, EOFA_EINVAL, "EOFA_MIXED_FP16 needs Ns in {8, 16, 32}");
     if (P.pc == EOFA_PC_LEARNED) {
         REQUIRE(ctx->cnn.ready, EOFA_ESTATE, "learned preconditioner: no weights (eofa_cnn_init or eofa_set_precond)");
         REQUIRE(ctx->Ns % 8 == 0, EOFA_EINVAL, "learned preconditioner needs Ns % 8 == 0");
     }
-    return solve_dt_fp64(ctx, W, mp, mm, P);
+    return solve_dt_fp64(ctx, W, mp, mm, P, guess);
 }
 
 void fill_info(eofa_solve_info* info, const SolveOut& so, double secs) {
@@ -1230,15 +1241,19 @@ void check_action(eofa_ctx* ctx, int chir, double m3, double m4, double mo, cons
 }
 
 // One chiral action; writes (accumulate = 0) or adds (accumulate = 1) its P_chir part into out.
+// x0 (optional): the two internal halves of a start vector for the 5D solve.
 eofa_status chiral_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi, void* out,
-                        int accumulate, double* S, const eofa_solve_params* P, eofa_solve_info* info) {
+                        int accumulate, double* S, const eofa_solve_params* P, eofa_solve_info* info,
+                        cd* const* x0 = nullptr) {
     check_params(ctx, P);
     check_action(ctx, chir, m3, m4, mo, phi, out);
     auto t0 = std::chrono::steady_clock::now();
     ensure_ws(ctx, needed_bytes(ctx, P));
     Work64 W = carve64(ctx);
     make_source(ctx, W, chir, phi);
-    SolveOut so = solve_dt(ctx, W, m3, m4, *P);
+    if (x0)
+        for (int par = 0; par < 2; par++) HIPCHK(launch_copy(W.x.h[par], x0[par], ctx->nh * sizeof(cd), ctx->st));
+    SolveOut so = solve_dt(ctx, W, m3, m4, *P, x0 != nullptr);
     const double s = combine(ctx, W, chir, action_k(chir, m3, m4, mo), phi, out, accumulate);
     if (S) *S = s;
     collect_timing(ctx);
@@ -1797,18 +1812,22 @@ void pack_gauge(eofa_ctx* ctx, const cd* U) {
 }
 
 // Solve and force of one chiral action into force[mu][site][8] (both parities' links).
+// x0 (optional): start vector of the solve (internal halves); xsave (optional): receives the solution.
 eofa_status chiral_force_impl(eofa_ctx* ctx, int chir, double m3, double m4, double mo, const void* phi,
-                              double* force, double* S, const eofa_solve_params* params, eofa_solve_info* info) {
+                              double* force, double* S, const eofa_solve_params* params, eofa_solve_info* info,
+                              cd* const* x0 = nullptr, cd* const* xsave = nullptr) {
     check_params(ctx, params);
     REQUIRE(ctx->gauge, EOFA_ESTATE, "no gauge field set");
     ensure_ws(ctx, needed_bytes(ctx, params));
     Work64 W = carve64(ctx);
     // the 4D output of the action is not needed: a workspace field (written after the solve) takes it
-    eofa_status st = chiral_impl(ctx, chir, m3, m4, mo, phi, (void*)W.res.h[0], 0, S, params, info);
+    eofa_status st = chiral_impl(ctx, chir, m3, m4, mo, phi, (void*)W.res.h[0], 0, S, params, info, x0);
     if (st != EOFA_OK && st != EOFA_ENOCONV) return st;
     const double kappa = chir * action_k(chir, m3, m4, mo);
     for (int par = 0; par < 2; par++)
         HIPCHK(launch_force(W.x.h[par], W.x.h[1 - par], ctx->U[par], ctx->g, par, ctx->Ns, kappa, force, ctx->st));
+    if (xsave)
+        for (int par = 0; par < 2; par++) HIPCHK(launch_copy(xsave[par], W.x.h[par], ctx->nh * sizeof(cd), ctx->st));
     return st;
 }
 
@@ -1851,6 +1870,8 @@ struct MdRun {
     double Sf_flush = 0;
     bool all = false;
     bool sf0 = false;  // info->Sf0 was taken from the first flush
+    // chronological start vectors: the last solution of each action in this trajectory (md->chrono)
+    std::vector<bool> have;
 };
 
 constexpr double kOmelyanLambda = 0.1931833275037836;
@@ -1880,7 +1901,10 @@ void md_flush(MdRun& m) {
             if (a.level != level) continue;
             eofa_solve_info si{};
             double S = 0;
-            const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, &S, m.sp, &si);
+            cd* const* g = m.md->chrono ? &ctx->md_guess[2 * i] : nullptr;
+            const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, &S, m.sp, &si,
+                                                     g && m.have[i] ? g : nullptr, g);
+            if (g) m.have[i] = true;
             m.info->cg_iters += si.iters;
             if (st != EOFA_OK) {
                 m.st = st;
@@ -2067,7 +2091,14 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
         const size_t nU = 72 * (size_t)ctx->g.Vh;  // complex entries of the canonical links
         if (!ctx->md_F) HIPCHK(hipMalloc(&ctx->md_F, sizeof(double) * md_len(ctx)));
         if (md->metropolis_u >= 0 && !ctx->md_U0) HIPCHK(hipMalloc(&ctx->md_U0, sizeof(cd) * nU));
+        if (md->chrono)
+            while ((int)ctx->md_guess.size() < 2 * nact) {
+                cd* q = nullptr;
+                HIPCHK(hipMalloc(&q, ctx->nh * sizeof(cd)));
+                ctx->md_guess.push_back(q);
+            }
         MdRun m{ctx, (cd*)U, P, nact, acts, md, solve, info};
+        m.have.assign(nact, false);
         if (md->metropolis_u >= 0) HIPCHK(launch_copy(ctx->md_U0, U, sizeof(cd) * nU, ctx->st));
         pack_gauge(ctx, (const cd*)U);
         info->K0 = kinetic_dev(ctx, P);
@@ -2605,6 +2636,7 @@ void eofa_destroy(eofa_ctx* ctx) {
     if (ctx->hb) (void)hipFree(ctx->hb);
     if (ctx->md_F) (void)hipFree(ctx->md_F);
     if (ctx->md_U0) (void)hipFree(ctx->md_U0);
+    for (cd* q : ctx->md_guess) (void)hipFree(q);
     if (ctx->partials_mr) (void)hipFree(ctx->partials_mr);
     {
         auto& c = ctx->cnn;

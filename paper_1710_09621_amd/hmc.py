@@ -46,6 +46,10 @@ def main():
     ap.add_argument("--prec", choices=("fp64", "fp16"), default="fp16")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--out", default=None, help="also write the lines to this file")
+    ap.add_argument("--no-chrono", action="store_true",
+                    help="start every force solve from zero instead of the action's previous solution")
+    ap.add_argument("--burn", type=int, default=0,
+                    help="trajectories left out of the equilibrium averages (<exp(-dH)>, acceptance, plaquette)")
     args = ap.parse_args()
 
     import numpy as np
@@ -82,7 +86,7 @@ def main():
         t_hb = time.perf_counter() - t0
         u = float(rng.random())
         md = ctx.md_trajectory(U, P, [a + (phis[i],) for i, a in enumerate(acts)], args.beta, args.tau,
-                               args.steps, metropolis_u=u, p=p)
+                               args.steps, metropolis_u=u, p=p, chrono=not args.no_chrono)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         plaq = 1.0 - ctx.gauge_action(U, 1.0) / (6 * Lx * Ly * Lz * Lt)
@@ -93,10 +97,22 @@ def main():
         lines.append(line)
         print(json.dumps(line), flush=True)
     summary = dict(lattice="x".join(map(str, dims)), Ns=Ns, scheme=args.scheme, actions=[list(a) for a in acts],
-                   beta=args.beta, steps=args.steps, prec=args.prec, ntraj=args.ntraj,
+                   beta=args.beta, steps=args.steps, prec=args.prec, ntraj=args.ntraj, chrono=not args.no_chrono,
                    accepted=sum(1 for x in lines if x["accepted"] == 1),
                    mean_s=round(sum(x["seconds"] for x in lines) / len(lines), 3),
                    mean_cg=round(sum(x["cg_iters"] for x in lines) / len(lines), 1))
+    eq = lines[args.burn:]
+    if len(eq) >= 2:
+        # every proposal counts in <exp(-dH)>, which is 1 in equilibrium for a reversible, area-preserving
+        # integrator; jackknife error over single trajectories
+        w = np.exp(-np.array([x["dH"] for x in eq]))
+        n = len(w)
+        jk = (w.sum() - w) / (n - 1)
+        err = float(np.sqrt((n - 1) / n * np.sum((jk - jk.mean()) ** 2)))
+        summary.update(burn=args.burn, exp_mdH=float(w.mean()), exp_mdH_err=err,
+                       acceptance=sum(1 for x in eq if x["accepted"] == 1) / n,
+                       plaquette=float(np.mean([x["plaquette"] for x in eq])),
+                       mean_abs_dH=float(np.mean([abs(x["dH"]) for x in eq])))
     print(json.dumps(dict(summary=summary)), flush=True)
     if args.out:
         with open(args.out, "w") as f:

@@ -4,6 +4,7 @@
     python -m paper_1710_09621_amd.profile_summary traffic FETCH_DIR WRITE_DIR OUT_JSON "FETCH_COMMAND" "WRITE_COMMAND" \
         [FETCH_STDOUT]
     python -m paper_1710_09621_amd.profile_summary hmc DIR RUN1.jsonl,RUN2.jsonl OUT_MD "TRACE_COMMAND" "RUN_COMMAND"
+    python -m paper_1710_09621_amd.profile_summary hmc_eq RUN.jsonl OUT_MD "RUN_COMMAND"
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
 dominant kernel (the FP64 hop K1 of the schedule the bench picked), the average duration of its launches in
@@ -220,6 +221,32 @@ def hmc(d, runs, out_md, command, run_command):
     print(out_md, {k: round(v / 1e6, 1) for k, v in split.items()})
 
 
+def hmc_eq(run, out_md, run_command):
+    """Thermalisation history and equilibrium averages of a long hmc.py run (--out file)."""
+    with open(run) as f:
+        rows = [json.loads(ln) for ln in f if ln.strip()]
+    summ = [r["summary"] for r in rows if "summary" in r][0]
+    traj = [r for r in rows if "summary" not in r]
+    lines = [f"# HMC equilibrium check on {summ['lattice']}, Ns = {summ['Ns']} ({summ['scheme']} MP)", "",
+             "Command (repository root, GPU box):", "", f"    {run_command}", "",
+             f"beta = {summ['beta']}, (k0, k1, k2) = {tuple(summ['steps'])}, actions (level, chir, m3, m4, mo) = "
+             f"{summ['actions']}, {summ['prec']} solves to 1e-10, chronological start vectors: {summ.get('chrono')}.", "",
+             f"Over the {summ['ntraj'] - summ['burn']} trajectories after the first {summ['burn']}:", "",
+             f"- <exp(-dH)> = {summ['exp_mdH']:.4f} +- {summ['exp_mdH_err']:.4f} (1 in equilibrium for a reversible, "
+             "area-preserving integrator)",
+             f"- acceptance {summ['acceptance']:.3f}, mean |dH| {summ['mean_abs_dH']:.4f}",
+             f"- plaquette {summ['plaquette']:.4f}; mean time per trajectory {summ['mean_s']:.3f} s, "
+             f"{summ['mean_cg']:.0f} CG iterations", "",
+             "| trajectory | plaquette | dH | accepted | CG iterations | seconds |", "|---:|---:|---:|---:|---:|---:|"]
+    for i, r in enumerate(traj):
+        if i < 10 or i % 10 == 0 or i == len(traj) - 1:
+            lines.append(f"| {r['traj']} | {r['plaquette']:.4f} | {r['dH']:.4f} | {r['accepted']} | {r['cg_iters']} | "
+                         f"{r['seconds']:.3f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out_md)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(*sys.argv[2:6])
@@ -227,5 +254,7 @@ if __name__ == "__main__":
         traffic(*sys.argv[2:8])
     elif sys.argv[1] == "hmc":
         hmc(*sys.argv[2:7])
+    elif sys.argv[1] == "hmc_eq":
+        hmc_eq(*sys.argv[2:5])
     else:
         raise SystemExit(__doc__)

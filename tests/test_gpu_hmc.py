@@ -159,3 +159,25 @@ def test_md_bad_arguments_are_einval(bad):
         ctx.md_trajectory(Ug, Pg, **kw)
     assert e.value.status == E.EINVAL
     assert torch.equal(Ug, U0)
+
+
+def test_chronological_start_vectors():
+    """Force solves started from the action's previous solution reach the same trajectory (within the solver
+    tolerance) with fewer CG iterations."""
+    from paper_1710_09621_amd import eofa as E
+    dims, Ns = (4, 4, 4, 4), 4
+    ctx, U, _ = _setup(dims, Ns, 0.5, 25)
+    acts = _fermion_case(dims, Ns, 26)
+    P = _momenta(dims, 27)
+    dev = torch.device("cuda")
+    out = []
+    for chrono in (False, True):
+        Ug = torch.from_numpy(U.copy()).to(dev)
+        Pg = torch.from_numpy(P.copy()).to(dev)
+        info = ctx.md_trajectory(Ug, Pg, acts, 5.7, 0.5, [8, 4, 2], p=E.params(tol=1e-12), chrono=chrono)
+        out.append((info, Ug.cpu().numpy(), Pg.cpu().numpy()))
+        print(f"  chrono={chrono}: cg {info['cg_iters']} dH {info['dH']:.9e}", flush=True)
+    (a, Ua, Pa), (b, Ub, Pb) = out
+    assert np.abs(Ua - Ub).max() < 1e-10 and np.abs(Pa - Pb).max() < 1e-9
+    assert abs(a["dH"] - b["dH"]) < 1e-8
+    assert b["cg_iters"] < a["cg_iters"]
