@@ -269,7 +269,9 @@ typedef struct {
  * last force evaluations.
  * U (device, canonical, in/out: the end point, or the start after a rejection) and P (device, in/out: the end
  * momenta) are caller-owned; every solve uses `solve`.  The context's gauge field follows U.  EINVAL for bad
- * levels, steps or arguments; a solve that does not converge stops the trajectory with its status.
+ * levels, steps or arguments; a solve that does not converge stops the trajectory with its status, with U (and
+ * the context's links) back at the start and P partly updated.  The library keeps one copy of the links
+ * (allocated on first use).
  */
 eofa_status eofa_md_trajectory(eofa_ctx *ctx, void *U, double *P, int nact, const eofa_md_action *acts,
                                const eofa_md_params *md, const eofa_solve_params *solve, eofa_md_info *info);

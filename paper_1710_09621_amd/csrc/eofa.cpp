@@ -2090,7 +2090,7 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
         info->accepted = -1;
         const size_t nU = 72 * (size_t)ctx->g.Vh;  // complex entries of the canonical links
         if (!ctx->md_F) HIPCHK(hipMalloc(&ctx->md_F, sizeof(double) * md_len(ctx)));
-        if (md->metropolis_u >= 0 && !ctx->md_U0) HIPCHK(hipMalloc(&ctx->md_U0, sizeof(cd) * nU));
+        if (!ctx->md_U0) HIPCHK(hipMalloc(&ctx->md_U0, sizeof(cd) * nU));
         if (md->chrono)
             while ((int)ctx->md_guess.size() < 2 * nact) {
                 cd* q = nullptr;
@@ -2099,12 +2099,21 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
             }
         MdRun m{ctx, (cd*)U, P, nact, acts, md, solve, info};
         m.have.assign(nact, false);
-        if (md->metropolis_u >= 0) HIPCHK(launch_copy(ctx->md_U0, U, sizeof(cd) * nU, ctx->st));
+        HIPCHK(launch_copy(ctx->md_U0, U, sizeof(cd) * nU, ctx->st));
         pack_gauge(ctx, (const cd*)U);
         info->K0 = kinetic_dev(ctx, P);
         info->Sg0 = gauge_action_dev(ctx, (const cd*)U, md->beta);
-        md_integrate(m, md->nlevels - 1, md->tau);
-        md_flush(m);  // the last kicks, at U(tau)
+        try {
+            md_integrate(m, md->nlevels - 1, md->tau);
+            md_flush(m);  // the last kicks, at U(tau)
+        } catch (const Fail&) {  // a solve failed: hand back the starting links (P holds the partial update)
+            const std::string why = ctx->err;
+            HIPCHK(launch_copy(U, ctx->md_U0, sizeof(cd) * nU, ctx->st));
+            pack_gauge(ctx, (const cd*)U);
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            ctx->err = why;
+            throw;
+        }
         // every level kicks before the first link update and after the last one, so both flushes solved every
         // action; anything else is a defect of the integrator
         REQUIRE(m.sf0 && m.all, EOFA_EHIP, "internal: the end flushes did not evaluate every action");

@@ -181,3 +181,24 @@ def test_chronological_start_vectors():
     assert np.abs(Ua - Ub).max() < 1e-10 and np.abs(Pa - Pb).max() < 1e-9
     assert abs(a["dH"] - b["dH"]) < 1e-8
     assert b["cg_iters"] < a["cg_iters"]
+
+
+def test_failed_solve_restores_the_links():
+    """A force solve that cannot converge (max_iter forced tiny from the host) stops the trajectory with
+    ENOCONV and hands back the starting links; the context's links are those links again."""
+    from paper_1710_09621_amd import eofa as E
+    dims, Ns = (4, 4, 4, 4), 4
+    ctx, U, _ = _setup(dims, Ns, 0.5, 28)
+    acts = _fermion_case(dims, Ns, 29)
+    dev = torch.device("cuda")
+    Ug = torch.from_numpy(U.copy()).to(dev)
+    Pg = torch.from_numpy(_momenta(dims, 30)).to(dev)
+    with pytest.raises(E.EofaError) as e:
+        ctx.md_trajectory(Ug, Pg, acts, 5.7, 0.5, [8, 4, 2], p=E.params(tol=1e-12, max_iter=5))
+    assert e.value.status == E.ENOCONV
+    assert np.array_equal(Ug.cpu().numpy(), U)
+    # the packed links follow: a chiral action now equals the one on a fresh context with U
+    ctx2, _, _ = _setup(dims, Ns, 0.5, 28)
+    a = ctx.chiral_action(+1, 0.05, 0.3, 1.0, acts[0][5], E.params(tol=1e-12))
+    b = ctx2.chiral_action(+1, 0.05, 0.3, 1.0, acts[0][5], E.params(tol=1e-12))
+    assert a.S == b.S
