@@ -13,8 +13,9 @@ epilogue) over the timed steps.
 Once per invocation, outside the timed steps, the whole sequence is solved to a true residual of 1e-10 on one
 Gaussian source in plain FP64 CG and in the tuned solver (the three systems in one multi-RHS launch sequence,
 FP16-column Krylov storage with FP32 arithmetic and FP64 reliable updates, autotuned schedules, hipGraph blocks
-of 16 iterations); their times and iteration counts go into "tts".  Inputs are generated on the host and moved
-to HBM before anything is timed.  Prints one JSON line.
+of 16 iterations); their times and iteration counts go into "tts".  Then one HMC trajectory of the same
+splitting on the 16^3 x 32 workload (heat-bath, three-scale Omelyan molecular dynamics, Metropolis) goes into
+"hmc".  Inputs are generated on the host and moved to HBM before anything is timed.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -114,6 +115,35 @@ def learned_leg(E, IN, ctx, Ns, omega, eps, action, phi_d, plain, max_iter):
                     "CG-iterate residual->error pairs of 4 seeded 8^4 fields (400 Adam steps)"}
 
 
+def hmc_leg(E, IN, max_iter):
+    """One HMC trajectory of one-flavour QCD with the new-MP splitting (Sec. I; Sec. III) on the 16^3 x 32,
+    Ns = 16 workload: heat-bath of the three chiral actions, the molecular dynamics with the Omelyan integrator
+    on the time scales (k0, k1, k2) = (480, 12, 6) of Sec. III, and the Metropolis test; FP16-storage solves to
+    1e-10 with chronological starts.  The start field is the synthetic one (not thermalised)."""
+    import numpy as np
+    import torch
+    from paper_1710_09621_amd import hmc as HM
+    from paper_1710_09621_amd import mpseq
+    cfg = IN.CONFIGS[2]
+    dims, Ns = tuple(cfg["dims"]), cfg["Ns"]
+    Lx, Ly, Lz, Lt = dims
+    U = torch.from_numpy(IN.gauge_links(dims, cfg["eps"], cfg["seed"]).reshape(Lt, Lz, Ly, Lx, 4, 3, 3)).cuda()
+    ctx = E.Context(dims, Ns, IN.M0, IN.optimal_omega(Ns))
+    ctx.set_gauge(U)
+    p = E.params(tol=1e-10, prec=E.MIXED_FP16, max_iter=max_iter)
+    acts = HM.levels(mpseq.actions("new", 0.01, [0.1], 1.0))
+    rec = HM.trajectory(ctx, U, acts, np.random.Generator(np.random.PCG64(1)), 6.2, 1.0, [480, 12, 6], p)
+    log(f"  [hmc] trajectory {rec['seconds']:.2f}s (heat-bath {rec['heatbath_s']:.2f}s, MD {rec['md_s']:.2f}s), "
+        f"dH={rec['dH']:.3f}, {rec['cg_iters']} CG iterations")
+    del ctx
+    torch.cuda.empty_cache()
+    return dict(lattice="x".join(map(str, dims)), Ns=Ns, beta=6.2, steps=[480, 12, 6],
+                actions=[list(a) for a in acts], seconds=rec["seconds"], heatbath_s=rec["heatbath_s"],
+                md_s=rec["md_s"], cg_iters=rec["cg_iters"], force_evals=rec["force_evals"],
+                link_updates=rec["link_updates"], dH=round(rec["dH"], 6), accepted=rec["accepted"],
+                form="heat-bath + Omelyan MD on 3 time scales + Metropolis, FP16-storage solves, chronological starts")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +154,7 @@ def main():
     ap.add_argument("--no-tts", action="store_true", help="skip the once-per-run time-to-solution comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner leg of the time to solution")
+    ap.add_argument("--no-hmc", action="store_true", help="skip the HMC trajectory leg")
     ap.add_argument("--max-iter", type=int, default=50000)
     ap.add_argument("--tune-cache", type=str, default=None)
     ap.add_argument("--tuned-prec", choices=("fp16", "fp32"), default="fp16",
@@ -236,6 +267,10 @@ def main():
         if not args.no_learned:
             tts["learned"] = learned_leg(E, IN, ctx, Ns, omega, eps, step_action, phi_d, plain[1], args.max_iter)
 
+    hmc = None
+    if not args.no_hmc:
+        hmc = hmc_leg(E, IN, args.max_iter)
+
     sched64 = tune["fp64"]["sched"]
     traffic = measured_traffic(args.traffic, dims, Ns, sched64)
     kern = {3: "k_hop_tw<16, false, HM_SITE, false, double, false> (u = A_T^{-1} H_eo p; t-walk schedule)",
@@ -280,6 +315,7 @@ def main():
                                           "gbs": round(v["bytes"] / max(v["ms"], 1e-12) / 1e6, 1)}
                                      for nm, v in kt.items()}},
         "tts": tts,
+        "hmc": hmc,
         "schedules": {k: v["sched"] for k, v in tune.items()},
         "cpu_baseline": cpu,
     }

@@ -30,6 +30,36 @@ def levels(acts):
     return [(1 if i == len(acts) - 1 else 2,) + tuple(a) for i, a in enumerate(acts)]
 
 
+def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True):
+    """One HMC trajectory in place on U (device links): momenta and noise from rng, the heat-bath of every
+    action, the molecular dynamics and the Metropolis test.  Returns the trajectory's record."""
+    import numpy as np
+    import torch
+    Lx, Ly, Lz, Lt = ctx.dims
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = torch.from_numpy(rng.standard_normal((4, Lt, Lz, Ly, Lx, 8))).cuda()
+    phis, hb = [], []
+    for (lev, chir, m3, m4, mo) in acts:
+        eta = (rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)) + 1j * rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)))
+        eta *= np.sqrt(0.5)  # weight exp(-eta^dag eta)
+        phi, info = ctx.chiral_heatbath(chir, m3, m4, mo, eta, p=p)
+        phis.append(phi)
+        hb.append(info)
+    torch.cuda.synchronize()
+    t_hb = time.perf_counter() - t0
+    u = float(rng.random())
+    md = ctx.md_trajectory(U, P, [a + (phis[i],) for i, a in enumerate(acts)], beta, tau, steps, metropolis_u=u,
+                           p=p, chrono=chrono)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    plaq = 1.0 - ctx.gauge_action(U, 1.0) / (6 * Lx * Ly * Lz * Lt)
+    return dict(dH=md["dH"], accepted=md["accepted"], u=u, plaquette=plaq, seconds=round(t, 3),
+                heatbath_s=round(t_hb, 3), md_s=round(md["seconds"], 3), cg_iters=md["cg_iters"],
+                force_evals=md["force_evals"][:len(steps)], link_updates=md["link_updates"],
+                hb_poles=[h["npoles"] for h in hb], H0=md["H0"], Sg0=md["Sg0"], Sf0=md["Sf0"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--config", type=int, default=2, help="synthetic start field and lattice (inputs.CONFIGS)")
@@ -72,28 +102,8 @@ def main():
     rng = np.random.Generator(np.random.PCG64(args.seed))
     lines = []
     for traj in range(args.ntraj):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        P = torch.from_numpy(rng.standard_normal((4, Lt, Lz, Ly, Lx, 8))).cuda()
-        phis, hb = [], []
-        for (lev, chir, m3, m4, mo) in acts:
-            eta = (rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)) + 1j * rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)))
-            eta *= np.sqrt(0.5)
-            phi, info = ctx.chiral_heatbath(chir, m3, m4, mo, eta, p=p)
-            phis.append(phi)
-            hb.append(info)
-        torch.cuda.synchronize()
-        t_hb = time.perf_counter() - t0
-        u = float(rng.random())
-        md = ctx.md_trajectory(U, P, [a + (phis[i],) for i, a in enumerate(acts)], args.beta, args.tau,
-                               args.steps, metropolis_u=u, p=p, chrono=not args.no_chrono)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
-        plaq = 1.0 - ctx.gauge_action(U, 1.0) / (6 * Lx * Ly * Lz * Lt)
-        line = dict(traj=traj, dH=md["dH"], accepted=md["accepted"], u=u, plaquette=plaq, seconds=round(t, 3),
-                    heatbath_s=round(t_hb, 3), md_s=round(md["seconds"], 3), cg_iters=md["cg_iters"],
-                    force_evals=md["force_evals"][:3], link_updates=md["link_updates"],
-                    hb_poles=[h["npoles"] for h in hb], H0=md["H0"], Sg0=md["Sg0"], Sf0=md["Sf0"])
+        line = dict(traj=traj, **trajectory(ctx, U, acts, rng, args.beta, args.tau, args.steps, p,
+                                            chrono=not args.no_chrono))
         lines.append(line)
         print(json.dumps(line), flush=True)
     summary = dict(lattice="x".join(map(str, dims)), Ns=Ns, scheme=args.scheme, actions=[list(a) for a in acts],
