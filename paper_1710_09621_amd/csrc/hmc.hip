@@ -170,50 +170,63 @@ __global__ __launch_bounds__(256) void k_plaquette(const cd* __restrict__ U, Geo
     finish_sum(red, block_sum256(v, lds));
 }
 
+// Four lanes per link (a quad of consecutive lanes): lane nu forms the two staples of the plane (mu, nu) (none when
+// nu == mu), the quad sums them, and every lane forms M = U A and writes two of the eight components.
 __global__ __launch_bounds__(256) void k_gauge_force(const cd* __restrict__ U, Geom g, double beta,
                                                      double* __restrict__ F, double* __restrict__ P, double h,
                                                      int kick) {
     const int V = 2 * g.Vh;
     const int tid = blockIdx.x * 256 + threadIdx.x;
-    if (tid >= 4 * V) return;
-    const int mu = tid / V, lex = tid - mu * V;
+    const int link = tid >> 2, nu = tid & 3;
+    const bool valid = link < 4 * V;  // whole quads are in or out: 4 V links, 256-lane blocks
+    const int mu = valid ? link / V : 0, lex = valid ? link - mu * V : 0;
     cd A[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) A[k] = {0, 0};
-    const int xm = lex_step(g, lex, mu, +1);
-#pragma unroll 1
-    for (int nu = 0; nu < 4; nu++) {
-        if (nu == mu) continue;
-        cd a[9], b[9], c[9], t[9], u[9];
+    if (valid && nu != mu) {
+        cd a[9], b[9], c[9], t[9];
+        const int xm = lex_step(g, lex, mu, +1);
         // upper staple U_nu(x + mu) U_mu(x + nu)^dag U_nu(x)^dag
         load_su3(U, xm, nu, a);
         load_su3(U, lex_step(g, lex, nu, +1), mu, b);
         load_su3(U, lex, nu, c);
         mul_nd(a, b, t);
-        mul_nd(t, c, u);
-#pragma unroll
-        for (int k = 0; k < 9; k++) A[k] = cadd(A[k], u[k]);
+        mul_nd(t, c, A);
         // lower staple U_nu(x + mu - nu)^dag U_mu(x - nu)^dag U_nu(x - nu) = (U_mu(x - nu) U_nu(x + mu - nu))^dag U_nu(x - nu)
         const int xd = lex_step(g, lex, nu, -1);
         load_su3(U, lex_step(g, xm, nu, -1), nu, a);
         load_su3(U, xd, mu, b);
         load_su3(U, xd, nu, c);
         mul_nn(b, a, t);
-        mul_dn(t, c, u);
+        mul_dn(t, c, a);
 #pragma unroll
-        for (int k = 0; k < 9; k++) A[k] = cadd(A[k], u[k]);
+        for (int k = 0; k < 9; k++) A[k] = cadd(A[k], a[k]);
     }
+    // quad sum ((A_0 + A_1) + (A_2 + A_3)), the same order in every lane
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        A[k].x += __shfl_xor(A[k].x, 1, 4);
+        A[k].y += __shfl_xor(A[k].y, 1, 4);
+        A[k].x += __shfl_xor(A[k].x, 2, 4);
+        A[k].y += __shfl_xor(A[k].y, 2, 4);
+    }
+    if (!valid) return;
     cd Um[9], M[9];
     load_su3(U, lex, mu, Um);
     mul_nn(Um, A, M);
     double o[8];
     im_tr_lambda(M, o);
     const double f = beta / 6.0;
-    double* q = (kick ? P : F) + (size_t)tid * 8;
-#pragma unroll
-    for (int a = 0; a < 8; a++) {
-        if (kick) q[a] -= h * f * o[a];
-        else q[a] = f * o[a];
+    // components 2 nu and 2 nu + 1 (selects: a runtime index would move o[] to scratch memory)
+    const double v0 = f * (nu == 0 ? o[0] : nu == 1 ? o[2] : nu == 2 ? o[4] : o[6]);
+    const double v1 = f * (nu == 0 ? o[1] : nu == 1 ? o[3] : nu == 2 ? o[5] : o[7]);
+    double* q = (kick ? P : F) + (size_t)link * 8 + 2 * nu;
+    if (kick) {
+        q[0] -= h * v0;
+        q[1] -= h * v1;
+    } else {
+        q[0] = v0;
+        q[1] = v1;
     }
 }
 
@@ -249,8 +262,9 @@ hipError_t launch_plaquette(const cd* U, const Geom& g, const Red& red, hipStrea
 
 hipError_t launch_gauge_force(const cd* U, const Geom& g, double beta, double* F, double* P, double h, int kick,
                               hipStream_t st) {
-    const int n = 8 * g.Vh;  // 4 V links
-    hipLaunchKernelGGL(k_gauge_force, dim3((n + 255) / 256), dim3(256), 0, st, U, g, beta, F, P, h, kick);
+    const long n = 4 * 8 * (long)g.Vh;  // four lanes per link, 4 V links
+    if (n > (1l << 31) - 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gauge_force, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, U, g, beta, F, P, h, kick);
     return hipGetLastError();
 }
 
