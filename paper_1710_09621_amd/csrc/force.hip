@@ -11,22 +11,22 @@
 
 namespace eofa {
 
-// (1 + sg gamma_mu) p in the chiral basis: upper += sg B_mu lower, lower += sg B_mu^dag upper.
-__device__ __forceinline__ void gamma_apply(cd o[12], const cd p[12], int mu, double sg) {
+// The upper half of (1 + sg gamma_mu) p in the chiral basis, h = u + sg B_mu d (u, d: spins 0-1 and 2-3).  Since
+// B_mu is unitary, the lower half is sg B_mu^dag h, so a spin-traced outer product with (1 + sg gamma_mu) p on one
+// side needs only h and the same projection of the other side (see k_force).
+__device__ __forceinline__ void half_proj(cd h[6], const cd p[12], int mu, double sg) {
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        const cd u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
-        cd b0, b1, t0, t1;  // B d and B^dag u
+        const cd d0 = p[6 + c], d1 = p[9 + c];
+        cd b0, b1;  // B d
         switch (mu) {
-        case 0: b0 = cneg(ci(d1)); b1 = cneg(ci(d0)); t0 = ci(u1); t1 = ci(u0); break;
-        case 1: b0 = cneg(d1); b1 = d0; t0 = u1; t1 = cneg(u0); break;
-        case 2: b0 = cneg(ci(d0)); b1 = ci(d1); t0 = ci(u0); t1 = cneg(ci(u1)); break;
-        default: b0 = d0; b1 = d1; t0 = u0; t1 = u1; break;
+        case 0: b0 = cneg(ci(d1)); b1 = cneg(ci(d0)); break;
+        case 1: b0 = cneg(d1); b1 = d0; break;
+        case 2: b0 = cneg(ci(d0)); b1 = ci(d1); break;
+        default: b0 = d0; b1 = d1; break;
         }
-        o[c] = {u0.x + sg * b0.x, u0.y + sg * b0.y};
-        o[3 + c] = {u1.x + sg * b1.x, u1.y + sg * b1.y};
-        o[6 + c] = {d0.x + sg * t0.x, d0.y + sg * t0.y};
-        o[9 + c] = {d1.x + sg * t1.x, d1.y + sg * t1.y};
+        h[c] = {p[c].x + sg * b0.x, p[c].y + sg * b0.y};
+        h[3 + c] = {p[3 + c].x + sg * b1.x, p[3 + c].y + sg * b1.y};
     }
 }
 
@@ -76,26 +76,34 @@ __global__ __launch_bounds__(256) void k_force(const cd* __restrict__ xown, cons
 #pragma unroll 1
     for (int mu = 0; mu < 4; mu++) {
         const int cbf = mu == 0 ? nb[0] : mu == 1 ? nb[2] : mu == 2 ? nb[4] : nb[6];
-        cd xf[12], yf[12], v[12], w[12];
+        // B1 = sum_sp [(1 - gamma) x(x+mu)]_sp (x) y_sp(x)^dag = sum over the two upper spins of a (x) z1^dag with
+        // a, z1 the upper halves of (1 - gamma) x(x+mu) and (1 - gamma) y(x); B2 likewise with (1 + gamma)
+        cd a[6], z2[6];
+        {
+            cd xf[12], yf[12];
 #pragma unroll
-        for (int j = 0; j < 12; j++) {
-            xf[j] = xoth[((size_t)cbf * 12 + j) * NS + s];
-            const cd b = xoth[((size_t)cbf * 12 + j) * NS + sb];
-            const double g5 = j < 6 ? 1.0 : -1.0;
-            yf[j] = {g5 * b.x, g5 * b.y};
+            for (int j = 0; j < 12; j++) {
+                xf[j] = xoth[((size_t)cbf * 12 + j) * NS + s];
+                const cd b = xoth[((size_t)cbf * 12 + j) * NS + sb];
+                const double g5 = j < 6 ? 1.0 : -1.0;
+                yf[j] = {g5 * b.x, g5 * b.y};
+            }
+            half_proj(a, xf, mu, -1.0);
+            half_proj(z2, yf, mu, +1.0);
         }
-        gamma_apply(v, xf, mu, -1.0);
-        gamma_apply(w, x0, mu, +1.0);
+        cd z1[6], c[6];
+        half_proj(z1, y0, mu, -1.0);
+        half_proj(c, x0, mu, +1.0);
         cd B1[9], B2[9];
 #pragma unroll
         for (int i = 0; i < 3; i++)
 #pragma unroll
-            for (int k = 0; k < 3; k++) {  // B[i][k] = sum_sp v[sp][i] conj(y[sp][k])
+            for (int k = 0; k < 3; k++) {  // B[i][k] = sum_sp h[sp][i] conj(z[sp][k])
                 cd b1 = {0, 0}, b2 = {0, 0};
 #pragma unroll
-                for (int sp = 0; sp < 4; sp++) {
-                    b1 = cjmadd(b1, y0[3 * sp + k], v[3 * sp + i]);
-                    b2 = cjmadd(b2, yf[3 * sp + k], w[3 * sp + i]);
+                for (int sp = 0; sp < 2; sp++) {
+                    b1 = cjmadd(b1, z1[3 * sp + k], a[3 * sp + i]);
+                    b2 = cjmadd(b2, z2[3 * sp + k], c[3 * sp + i]);
                 }
                 B1[3 * i + k] = b1;
                 B2[3 * i + k] = b2;

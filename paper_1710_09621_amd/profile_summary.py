@@ -5,6 +5,7 @@
         [FETCH_STDOUT]
     python -m paper_1710_09621_amd.profile_summary hmc DIR RUN1.jsonl,RUN2.jsonl OUT_MD "TRACE_COMMAND" "RUN_COMMAND"
     python -m paper_1710_09621_amd.profile_summary hmc_eq RUN.jsonl OUT_MD "RUN_COMMAND"
+    python -m paper_1710_09621_amd.profile_summary force DIR OUT_MD "COMMAND"
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
 dominant kernel (the FP64 hop K1 of the schedule the bench picked), the average duration of its launches in
@@ -221,6 +222,36 @@ def hmc(d, runs, out_md, command, run_command):
     print(out_md, {k: round(v / 1e6, 1) for k, v in split.items()})
 
 
+def force(d, out_md, command, dims=(32, 32, 32, 64), Ns=16):
+    """Kernel table of a rocprofv3 --stats run of profile_force.py and the fermion-force kernel's rate."""
+    stats = _rows(os.path.join(d, "**", "*kernel_stats.csv"))
+    total = sum(float(_col(r, "TotalDurationNs")) for r in stats)
+    stats.sort(key=lambda r: -float(_col(r, "TotalDurationNs")))
+    Lx, Ly, Lz, Lt = dims
+    V = Lx * Ly * Lz * Lt
+    lines = [f"# EOFA fermion force (k_force) on {'x'.join(map(str, dims))}, Ns = {Ns}", "",
+             "Command (repository root, GPU box):", "", f"    {command}", "",
+             "The driver computes the force of the new-MP middle action (+, 0.01, 0.1; 1.0) twice with the FP16-storage",
+             "solver; each force call launches `k_force` once per parity.", "",
+             "| kernel | calls | avg us | total % |", "|---|---:|---:|---:|"]
+    for r in stats[:10]:
+        nm = _col(r, "Name", "KernelName", "Kernel_Name").replace("|", "\\|")
+        lines.append(f"| `{nm[:100]}` | {_col(r, 'Calls')} | {float(_col(r, 'AverageNs')) / 1e3:.1f} | "
+                     f"{100 * float(_col(r, 'TotalDurationNs')) / total:.2f} |")
+    kf = [r for r in stats if f"k_force<{Ns}>" in _col(r, "Name", "KernelName", "Kernel_Name")][0]
+    avg = float(_col(kf, "AverageNs")) / 1e3
+    # per launch (one parity's links): the 5D solution on both parities once, the links of one parity, the force out
+    alg = V * Ns * 12 * 16 + (V // 2) * 4 * 144 + (V // 2) * 4 * 8 * 8
+    lines += ["", f"`k_force<{Ns}>`: {_col(kf, 'Calls')} launches, average {avg:.1f} us per parity. Algorithmic bytes per "
+              f"launch (one parity's links): the 5D solution on both parities once ({V * Ns * 192 / 1e9:.2f} GB), the "
+              f"links of one parity ({(V // 2) * 576 / 1e9:.2f} GB) and the force of one parity "
+              f"({(V // 2) * 256 / 1e9:.3f} GB) = {alg / 1e9:.2f} GB, i.e. {alg / (avg * 1e-6) / 1e12:.2f} TB/s "
+              f"({100 * alg / (avg * 1e-6) / 8e12:.0f}% of 8 TB/s)."]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out_md, f"k_force {avg:.1f} us")
+
+
 def hmc_eq(run, out_md, run_command):
     """Thermalisation history and equilibrium averages of a long hmc.py run (--out file)."""
     with open(run) as f:
@@ -254,6 +285,8 @@ if __name__ == "__main__":
         traffic(*sys.argv[2:8])
     elif sys.argv[1] == "hmc":
         hmc(*sys.argv[2:7])
+    elif sys.argv[1] == "force":
+        force(*sys.argv[2:5])
     elif sys.argv[1] == "hmc_eq":
         hmc_eq(*sys.argv[2:5])
     else:
