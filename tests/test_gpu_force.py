@@ -56,3 +56,20 @@ def test_force_rejects_null(setup):
     p = E.params()
     st = ctx.lib.eofa_chiral_force(ctx.h, -1, 0.1, 0.1, 0.5, phi.data_ptr(), None, None, C.byref(p), None)
     assert st == E.EINVAL
+
+
+@pytest.mark.parametrize("chir,m3,m4,mo", [(+1, 0.3, 0.6, 1.0), (-1, 0.1, 0.1, 0.5)])
+def test_force_larger_lattice(chir, m3, m4, mo):
+    """8x8x2x16 at Ns = 8 (whole 256-lane workgroups per (z, t) line, 32 workgroups per parity): every component
+    against the oracle."""
+    from oracle import force as OF
+    from paper_1710_09621_amd import eofa as E
+    from paper_1710_09621_amd import inputs as IN
+    dims, Ns = (8, 8, 2, 16), 8
+    print(f"[gpu] force case dims={dims} Ns={Ns} action={(chir, m3, m4, mo)}", flush=True)
+    ctx, lat = ctx_and_oracle(dims, Ns)
+    phi = IN.gaussian_spinor(lat.shape4[:-2], 34)
+    F, S, info = ctx.chiral_force(chir, m3, m4, mo, phi, E.params(tol=1e-12, max_iter=20000))
+    ref = OF.force(lat, chir, m3, m4, mo, phi, tol=1e-12)
+    assert info["true_rel_resid"] <= 1e-12
+    assert np.abs(F.cpu().numpy() - ref).max() < 1e-9 * np.abs(ref).max()

@@ -202,3 +202,26 @@ def test_failed_solve_restores_the_links():
     a = ctx.chiral_action(+1, 0.05, 0.3, 1.0, acts[0][5], E.params(tol=1e-12))
     b = ctx2.chiral_action(+1, 0.05, 0.3, 1.0, acts[0][5], E.params(tol=1e-12))
     assert a.S == b.S
+
+
+def test_hmc_driver_trajectories():
+    """The trajectory driver of hmc.py (heat-bath of every action, molecular dynamics, Metropolis) on 4^4, Ns = 8:
+    two trajectories of the new-MP splitting with coarse steps; the links stay in SU(3)."""
+    from paper_1710_09621_amd import eofa as E
+    from paper_1710_09621_amd import hmc as HM
+    from paper_1710_09621_amd import mpseq
+    dims, Ns = (4, 4, 4, 4), 8
+    ctx, U, _ = _setup(dims, Ns, 0.3, 31)
+    Ug = torch.from_numpy(U.copy()).cuda()
+    acts = HM.levels(mpseq.actions("new", 0.05, [0.3], 1.0))
+    rng = np.random.Generator(np.random.PCG64(32))
+    p = E.params(tol=1e-10, prec=E.MIXED_FP16)
+    for _ in range(2):
+        rec = HM.trajectory(ctx, Ug, acts, rng, 5.7, 1.0, [16, 4, 2], p)
+        print(f"  trajectory dH {rec['dH']:.4f} accepted {rec['accepted']} cg {rec['cg_iters']} poles {rec['hb_poles']}",
+              flush=True)
+        assert rec["accepted"] in (0, 1) and np.isfinite(rec["dH"]) and rec["cg_iters"] > 0
+        assert rec["force_evals"] == [33, 9, 5] and len(rec["hb_poles"]) == 3
+    Un = Ug.cpu().numpy()
+    assert np.abs(np.conj(np.swapaxes(Un, -1, -2)) @ Un - np.eye(3)).max() < 1e-12
+    assert np.abs(np.linalg.det(Un) - 1).max() < 1e-12
