@@ -141,6 +141,7 @@ def hmc_leg(E, IN, max_iter):
                 actions=[list(a) for a in acts], seconds=rec["seconds"], heatbath_s=rec["heatbath_s"],
                 md_s=rec["md_s"], cg_iters=rec["cg_iters"], force_evals=rec["force_evals"],
                 link_updates=rec["link_updates"], dH=round(rec["dH"], 6), accepted=rec["accepted"],
+                force_max=rec["force_max"], gauge_force0=rec["gauge_force0"],
                 form="heat-bath + Omelyan MD on 3 time scales + Metropolis, FP16-storage solves, chronological starts")
 
 

@@ -257,6 +257,11 @@ typedef struct {
     int link_updates;
     long cg_iters;               /* CG iterations of every solve of the trajectory (forces and actions) */
     double seconds;
+    /* force magnitudes, |F| = sqrt(sum_a F^a F^a) averaged over the links: per action (the first 8 of acts) the
+     * largest and the mean over its force evaluations in the trajectory, and the gauge force at the start */
+    double force_max[8];
+    double force_mean[8];
+    double gauge_force0;
 } eofa_md_info;
 /*
  * One molecular-dynamics trajectory from (U, P): the second-order minimum-norm (Omelyan) integrator nested over

@@ -86,6 +86,8 @@ struct eofa_ctx {
     double* md_F = nullptr;  // molecular dynamics: one force field, 4 V 8 doubles
     cd* md_U0 = nullptr;     // the links at the start of a trajectory (restored on rejection)
     std::vector<cd*> md_guess;  // chronological start vectors, two halves per action
+    double* md_fn = nullptr;    // link-summed |F| of every fermion force evaluation of a trajectory
+    size_t md_fn_len = 0;
     void* hb = nullptr;  // heat-bath: the 4D outputs of the shifted chiral actions
     size_t hb_bytes = 0;
     std::string err;
@@ -1872,6 +1874,9 @@ struct MdRun {
     bool sf0 = false;  // info->Sf0 was taken from the first flush
     // chronological start vectors: the last solution of each action in this trajectory (md->chrono)
     std::vector<bool> have;
+    // force magnitudes: action i's k-th evaluation goes to md_fn[off[i] + k]
+    std::vector<size_t> off;
+    std::vector<int> nev;
 };
 
 constexpr double kOmelyanLambda = 0.1931833275037836;
@@ -1912,6 +1917,12 @@ void md_flush(MdRun& m) {
             }
             m.Sf_flush += S;
             solved++;
+            if (i < (int)m.nev.size() && m.nev[i] < (int)(m.off[i + 1] - m.off[i])) {
+                const Red red{ctx->partials, ctx->md_fn, (int)(m.off[i] + m.nev[i]++), EPI_STORE};
+                const size_t nl = md_len(ctx) / 8;
+                HIPCHK(launch_link_norms(ctx->md_F, nl, red, ctx->st));
+                HIPCHK(launch_finish(red, (unsigned)((nl + 255) / 256), ctx->st));
+            }
             HIPCHK(launch_kick(m.P, ctx->md_F, h, md_len(ctx), ctx->st));
         }
     }
@@ -2099,10 +2110,32 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
             }
         MdRun m{ctx, (cd*)U, P, nact, acts, md, solve, info};
         m.have.assign(nact, false);
+        {   // one slot per force evaluation of each reported action (2 steps[level] + 1 of them)
+            const int nrep = nact < 8 ? nact : 8;
+            m.off.assign(nrep + 1, 0);
+            m.nev.assign(nrep, 0);
+            for (int i = 0; i < nrep; i++) m.off[i + 1] = m.off[i] + 2 * (size_t)md->steps[acts[i].level] + 1;
+            if (m.off[nrep] > ctx->md_fn_len) {
+                if (ctx->md_fn) HIPCHK(hipFree(ctx->md_fn));
+                ctx->md_fn = nullptr;
+                ctx->md_fn_len = 0;
+                HIPCHK(hipMalloc(&ctx->md_fn, sizeof(double) * m.off[nrep]));
+                ctx->md_fn_len = m.off[nrep];
+            }
+        }
         HIPCHK(launch_copy(ctx->md_U0, U, sizeof(cd) * nU, ctx->st));
         pack_gauge(ctx, (const cd*)U);
         info->K0 = kinetic_dev(ctx, P);
         info->Sg0 = gauge_action_dev(ctx, (const cd*)U, md->beta);
+        {   // the gauge force at the start, averaged over the links
+            const size_t nl = md_len(ctx) / 8;
+            const Red red = red_of(ctx, SC_TMP + 19, EPI_STORE);
+            HIPCHK(launch_gauge_force((const cd*)U, ctx->g, md->beta, ctx->md_F, nullptr, 0.0, 0, ctx->st));
+            HIPCHK(launch_link_norms(ctx->md_F, nl, red, ctx->st));
+            HIPCHK(launch_finish(red, (unsigned)((nl + 255) / 256), ctx->st));
+            sync_scal(ctx);
+            info->gauge_force0 = ctx->hscal[SC_TMP + 19] / (double)nl;
+        }
         try {
             md_integrate(m, md->nlevels - 1, md->tau);
             md_flush(m);  // the last kicks, at U(tau)
@@ -2118,6 +2151,22 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
         // action; anything else is a defect of the integrator
         REQUIRE(m.sf0 && m.all, EOFA_EHIP, "internal: the end flushes did not evaluate every action");
         info->Sf1 = m.Sf_flush;
+        if (!m.nev.empty()) {
+            std::vector<double> fn(m.off.back());
+            HIPCHK(hipMemcpyAsync(fn.data(), ctx->md_fn, sizeof(double) * fn.size(), hipMemcpyDeviceToHost, ctx->st));
+            HIPCHK(hipStreamSynchronize(ctx->st));
+            const double nl = (double)(md_len(ctx) / 8);
+            for (size_t i = 0; i < m.nev.size(); i++) {
+                double mx = 0, sum = 0;
+                for (int k = 0; k < m.nev[i]; k++) {
+                    const double v = fn[m.off[i] + k] / nl;
+                    mx = std::max(mx, v);
+                    sum += v;
+                }
+                info->force_max[i] = mx;
+                info->force_mean[i] = m.nev[i] ? sum / m.nev[i] : 0.0;
+            }
+        }
         info->K1 = kinetic_dev(ctx, P);
         info->Sg1 = gauge_action_dev(ctx, (const cd*)U, md->beta);
         info->H0 = info->K0 + info->Sg0 + info->Sf0;
@@ -2646,6 +2695,7 @@ void eofa_destroy(eofa_ctx* ctx) {
     if (ctx->md_F) (void)hipFree(ctx->md_F);
     if (ctx->md_U0) (void)hipFree(ctx->md_U0);
     for (cd* q : ctx->md_guess) (void)hipFree(q);
+    if (ctx->md_fn) (void)hipFree(ctx->md_fn);
     if (ctx->partials_mr) (void)hipFree(ctx->partials_mr);
     {
         auto& c = ctx->cnn;

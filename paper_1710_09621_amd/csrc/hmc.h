@@ -16,6 +16,10 @@ hipError_t launch_plaquette(const cd* U, const Geom& g, const Red& red, hipStrea
 hipError_t launch_gauge_force(const cd* U, const Geom& g, double beta, double* F, double* P, double h, int kick,
                               hipStream_t st);
 
+// partials[block] = sum over the block's links of |F| = sqrt(sum_a F^a F^a); one block per 256 links (then
+// launch_finish).
+hipError_t launch_link_norms(const double* F, size_t nlinks, const Red& red, hipStream_t st);
+
 // P -= h F over n doubles.
 hipError_t launch_kick(double* P, const double* F, double h, size_t n, hipStream_t st);
 

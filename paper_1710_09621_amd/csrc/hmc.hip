@@ -230,6 +230,20 @@ __global__ __launch_bounds__(256) void k_gauge_force(const cd* __restrict__ U, G
     }
 }
 
+// partials of sum over links of |F| = sqrt(sum_a F^a F^a) (one thread per link)
+__global__ __launch_bounds__(256) void k_link_norms(const double* __restrict__ F, size_t nlinks, Red red) {
+    __shared__ double lds[4];
+    const size_t l = (size_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0;
+    if (l < nlinks) {
+        const double* f = F + l * 8;
+#pragma unroll
+        for (int a = 0; a < 8; a++) v = fma(f[a], f[a], v);
+        v = sqrt(v);
+    }
+    finish_sum(red, block_sum256(v, lds));
+}
+
 __global__ __launch_bounds__(256) void k_kick(double* __restrict__ P, const double* __restrict__ F, double h, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) P[i] -= h * F[i];
 }
@@ -265,6 +279,12 @@ hipError_t launch_gauge_force(const cd* U, const Geom& g, double beta, double* F
     const long n = 4 * 8 * (long)g.Vh;  // four lanes per link, 4 V links
     if (n > (1l << 31) - 256) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gauge_force, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, U, g, beta, F, P, h, kick);
+    return hipGetLastError();
+}
+
+hipError_t launch_link_norms(const double* F, size_t nlinks, const Red& red, hipStream_t st) {
+    const size_t b = (nlinks + 255) / 256;
+    hipLaunchKernelGGL(k_link_norms, dim3((unsigned)b), dim3(256), 0, st, F, nlinks, red);
     return hipGetLastError();
 }
 

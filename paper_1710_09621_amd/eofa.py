@@ -79,11 +79,13 @@ class MdInfo(C.Structure):
     _fields_ = [("H0", C.c_double), ("H1", C.c_double), ("dH", C.c_double), ("K0", C.c_double),
                 ("K1", C.c_double), ("Sg0", C.c_double), ("Sg1", C.c_double), ("Sf0", C.c_double),
                 ("Sf1", C.c_double), ("accepted", C.c_int), ("force_evals", C.c_int * 4), ("link_updates", C.c_int),
-                ("cg_iters", C.c_long), ("seconds", C.c_double)]
+                ("cg_iters", C.c_long), ("seconds", C.c_double), ("force_max", C.c_double * 8),
+                ("force_mean", C.c_double * 8), ("gauge_force0", C.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["force_evals"] = list(self.force_evals)
+        for k in ("force_evals", "force_max", "force_mean"):
+            d[k] = list(getattr(self, k))
         return d
 
 

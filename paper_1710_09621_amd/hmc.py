@@ -1,6 +1,7 @@
 """HMC of one-flavour QCD with the exact one-flavor action and mass preconditioning (Sec. I; Sec. III).
 
     python -m paper_1710_09621_amd.hmc [--config 2] [--scheme new] [--ntraj 2] [--steps 480 12 6] [--beta 6.2]
+    python -m paper_1710_09621_amd.hmc --config 2 --therm 30 --compare --ntraj 4   # the three splittings of Sec. III
 
 Every trajectory follows the outline of Sec. I:
   (2) momenta P^a ~ N(0, 1) and (3) pseudofermion noise eta of weight exp(-eta^dag eta), drawn on the host from
@@ -10,7 +11,9 @@ Every trajectory follows the outline of Sec. I:
   (5) the molecular dynamics with the Omelyan integrator nested over three time scales and (6) the Metropolis
       test, both in eofa_md_trajectory.
 The levels follow Sec. III: the gauge field at k0, the last (heaviest) factor of the splitting at k1, the other
-factors at k2, with (k0, k1, k2) = (480, 12, 6).  Prints one JSON line per trajectory and a summary.
+factors at k2, with (k0, k1, k2) = (480, 12, 6).  Prints one JSON line per trajectory and a summary per splitting
+with the CG iterations, the time and the force magnitudes (|F| averaged over the links; per action the largest
+and the mean over its evaluations in a trajectory, and the gauge force), the quantities Sec. III compares.
 """
 from __future__ import annotations
 
@@ -54,10 +57,38 @@ def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     plaq = 1.0 - ctx.gauge_action(U, 1.0) / (6 * Lx * Ly * Lz * Lt)
+    n = min(len(acts), 8)
     return dict(dH=md["dH"], accepted=md["accepted"], u=u, plaquette=plaq, seconds=round(t, 3),
                 heatbath_s=round(t_hb, 3), md_s=round(md["seconds"], 3), cg_iters=md["cg_iters"],
                 force_evals=md["force_evals"][:len(steps)], link_updates=md["link_updates"],
-                hb_poles=[h["npoles"] for h in hb], H0=md["H0"], Sg0=md["Sg0"], Sf0=md["Sf0"])
+                hb_poles=[h["npoles"] for h in hb], H0=md["H0"], Sg0=md["Sg0"], Sf0=md["Sf0"],
+                force_max=[round(v, 6) for v in md["force_max"][:n]],
+                force_mean=[round(v, 6) for v in md["force_mean"][:n]], gauge_force0=round(md["gauge_force0"], 6))
+
+
+def summarize(lines, dims, Ns, scheme, acts, args):
+    import numpy as np
+    summary = dict(lattice="x".join(map(str, dims)), Ns=Ns, scheme=scheme, actions=[list(a) for a in acts],
+                   beta=args.beta, steps=args.steps, prec=args.prec, ntraj=len(lines), chrono=not args.no_chrono,
+                   accepted=sum(1 for x in lines if x["accepted"] == 1),
+                   mean_s=round(sum(x["seconds"] for x in lines) / len(lines), 3),
+                   mean_cg=round(sum(x["cg_iters"] for x in lines) / len(lines), 1),
+                   force_max=[round(float(v), 5) for v in np.mean([x["force_max"] for x in lines], axis=0)],
+                   force_mean=[round(float(v), 5) for v in np.mean([x["force_mean"] for x in lines], axis=0)],
+                   gauge_force0=round(float(np.mean([x["gauge_force0"] for x in lines])), 5))
+    eq = lines[args.burn:]
+    if len(eq) >= 2:
+        # every proposal counts in <exp(-dH)>, which is 1 in equilibrium for a reversible, area-preserving
+        # integrator; jackknife error over single trajectories
+        w = np.exp(-np.array([x["dH"] for x in eq]))
+        n = len(w)
+        jk = (w.sum() - w) / (n - 1)
+        err = float(np.sqrt((n - 1) / n * np.sum((jk - jk.mean()) ** 2)))
+        summary.update(burn=args.burn, exp_mdH=float(w.mean()), exp_mdH_err=err,
+                       acceptance=sum(1 for x in eq if x["accepted"] == 1) / n,
+                       plaquette=float(np.mean([x["plaquette"] for x in eq])),
+                       mean_abs_dH=float(np.mean([abs(x["dH"]) for x in eq])))
+    return summary
 
 
 def main():
@@ -66,6 +97,10 @@ def main():
     ap.add_argument("--dims", type=int, nargs=4, default=None)
     ap.add_argument("--Ns", type=int, default=None)
     ap.add_argument("--scheme", choices=("none", "old", "new"), default="new")
+    ap.add_argument("--compare", action="store_true",
+                    help="after --therm trajectories of --scheme, run --ntraj trajectories of each splitting (new, "
+                         "old, none), every one starting from the same thermalised field")
+    ap.add_argument("--therm", type=int, default=0, help="trajectories before the measured ones (reported as such)")
     ap.add_argument("--m", type=float, default=0.01)
     ap.add_argument("--mh", type=float, default=0.1)
     ap.add_argument("--M", type=float, default=1.0)
@@ -97,36 +132,36 @@ def main():
     ctx.set_gauge(U)
     prec = {"fp64": E.FP64, "fp16": E.MIXED_FP16}[args.prec]
     p = E.params(tol=1e-10, prec=prec, max_iter=50000)
-    heavies = [] if args.scheme == "none" else [args.mh]
-    acts = levels(mpseq.actions(args.scheme, args.m, heavies, args.M))
+
+    def splitting(kind):
+        return levels(mpseq.actions(kind, args.m, [] if kind == "none" else [args.mh], args.M))
+
     rng = np.random.Generator(np.random.PCG64(args.seed))
-    lines = []
-    for traj in range(args.ntraj):
-        line = dict(traj=traj, **trajectory(ctx, U, acts, rng, args.beta, args.tau, args.steps, p,
-                                            chrono=not args.no_chrono))
-        lines.append(line)
-        print(json.dumps(line), flush=True)
-    summary = dict(lattice="x".join(map(str, dims)), Ns=Ns, scheme=args.scheme, actions=[list(a) for a in acts],
-                   beta=args.beta, steps=args.steps, prec=args.prec, ntraj=args.ntraj, chrono=not args.no_chrono,
-                   accepted=sum(1 for x in lines if x["accepted"] == 1),
-                   mean_s=round(sum(x["seconds"] for x in lines) / len(lines), 3),
-                   mean_cg=round(sum(x["cg_iters"] for x in lines) / len(lines), 1))
-    eq = lines[args.burn:]
-    if len(eq) >= 2:
-        # every proposal counts in <exp(-dH)>, which is 1 in equilibrium for a reversible, area-preserving
-        # integrator; jackknife error over single trajectories
-        w = np.exp(-np.array([x["dH"] for x in eq]))
-        n = len(w)
-        jk = (w.sum() - w) / (n - 1)
-        err = float(np.sqrt((n - 1) / n * np.sum((jk - jk.mean()) ** 2)))
-        summary.update(burn=args.burn, exp_mdH=float(w.mean()), exp_mdH_err=err,
-                       acceptance=sum(1 for x in eq if x["accepted"] == 1) / n,
-                       plaquette=float(np.mean([x["plaquette"] for x in eq])),
-                       mean_abs_dH=float(np.mean([abs(x["dH"]) for x in eq])))
-    print(json.dumps(dict(summary=summary)), flush=True)
+    out = []
+
+    def emit(x):
+        out.append(x)
+        print(json.dumps(x), flush=True)
+
+    for traj in range(args.therm):
+        emit(dict(phase="therm", scheme=args.scheme, traj=traj,
+                  **trajectory(ctx, U, splitting(args.scheme), rng, args.beta, args.tau, args.steps, p,
+                               chrono=not args.no_chrono)))
+    start = U.clone()
+    for scheme in (("new", "old", "none") if args.compare else (args.scheme,)):
+        U.copy_(start)
+        ctx.set_gauge(U)
+        acts = splitting(scheme)
+        lines = []
+        for traj in range(args.ntraj):
+            line = dict(traj=traj, scheme=scheme, **trajectory(ctx, U, acts, rng, args.beta, args.tau, args.steps, p,
+                                                               chrono=not args.no_chrono))
+            lines.append(line)
+            emit(line)
+        emit(dict(summary=summarize(lines, dims, Ns, scheme, acts, args)))
     if args.out:
         with open(args.out, "w") as f:
-            for x in lines + [dict(summary=summary)]:
+            for x in out:
                 f.write(json.dumps(x) + "\n")
 
 

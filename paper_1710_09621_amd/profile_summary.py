@@ -5,6 +5,7 @@
         [FETCH_STDOUT]
     python -m paper_1710_09621_amd.profile_summary hmc DIR RUN1.jsonl,RUN2.jsonl OUT_MD "TRACE_COMMAND" "RUN_COMMAND"
     python -m paper_1710_09621_amd.profile_summary hmc_eq RUN.jsonl OUT_MD "RUN_COMMAND"
+    python -m paper_1710_09621_amd.profile_summary hmc_compare RUN.jsonl OUT_MD "RUN_COMMAND"
     python -m paper_1710_09621_amd.profile_summary force DIR OUT_MD "COMMAND"
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
@@ -252,6 +253,33 @@ def force(d, out_md, command, dims=(32, 32, 32, 64), Ns=16):
     print(out_md, f"k_force {avg:.1f} us")
 
 
+def hmc_compare(run, out_md, run_command):
+    """The three splittings from one thermalised field (hmc.py --therm N --compare): per splitting the time, CG
+    iterations, acceptance and the force magnitudes per action."""
+    with open(run) as f:
+        rows = [json.loads(ln) for ln in f if ln.strip()]
+    therm = [r for r in rows if r.get("phase") == "therm"]
+    summs = [r["summary"] for r in rows if "summary" in r]
+    lat = summs[0]
+    lines = [f"# The splittings of Sec. III from one thermalised field: {lat['lattice']}, Ns = {lat['Ns']}", "",
+             "Command (repository root, GPU box):", "", f"    {run_command}", "",
+             f"beta = {lat['beta']}, (k0, k1, k2) = {tuple(lat['steps'])}, {lat['prec']} solves to 1e-10, chronological "
+             f"start vectors: {lat['chrono']}. {len(therm)} thermalisation trajectories of the "
+             f"{therm[0]['scheme'] if therm else '-'} splitting (plaquette {therm[0]['plaquette'] if therm else 0:.4f} -> "
+             f"{therm[-1]['plaquette'] if therm else 0:.4f}); then every splitting runs {lat['ntraj']} trajectories from "
+             "the same field. ‖F‖ = sqrt(sum_a F^a F^a) averaged over the links; per action the largest over its force "
+             "evaluations in a trajectory (mean over the trajectories).", "",
+             "| splitting | actions (level, chir, m3, m4, mo) | seconds per trajectory | CG iterations | accepted | largest ‖F‖ per action | gauge ‖F‖ |",
+             "|---|---|---:|---:|---:|---|---:|"]
+    for sm in summs:
+        acts = "; ".join(f"({a[0]}, {a[1]:+d}, {a[2]}, {a[3]}, {a[4]})" for a in sm["actions"])
+        lines.append(f"| {sm['scheme']} | {acts} | {sm['mean_s']:.2f} | {sm['mean_cg']:.0f} | {sm['accepted']}/{sm['ntraj']} | "
+                     f"{', '.join(f'{v:.4f}' for v in sm['force_max'])} | {sm['gauge_force0']:.3f} |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out_md)
+
+
 def hmc_eq(run, out_md, run_command):
     """Thermalisation history and equilibrium averages of a long hmc.py run (--out file)."""
     with open(run) as f:
@@ -287,6 +315,8 @@ if __name__ == "__main__":
         hmc(*sys.argv[2:7])
     elif sys.argv[1] == "force":
         force(*sys.argv[2:5])
+    elif sys.argv[1] == "hmc_compare":
+        hmc_compare(*sys.argv[2:5])
     elif sys.argv[1] == "hmc_eq":
         hmc_eq(*sys.argv[2:5])
     else:

@@ -89,6 +89,13 @@ def test_fermion_trajectory():
     info, _, _ = _compare_trajectory(ctx, sysm, U, P, 0.25, acts, steps, 1e-9, 1e-7, p=E.params(tol=1e-12))
     assert info["cg_iters"] > 0
     assert info["Sf0"] > 0 and info["Sg0"] > 0
+    # force magnitudes: the link average of |F| of each action, largest and mean over its evaluations
+    import oracle.hmc as OH
+    Fg = OH.gauge_force(U, dims, 5.7)
+    assert info["gauge_force0"] == pytest.approx(float(np.sqrt((Fg ** 2).sum(-1)).mean()), rel=1e-10)
+    for i in range(2):
+        assert 0 < info["force_mean"][i] <= info["force_max"][i]
+    assert info["force_max"][2:] == [0.0] * 6
 
 
 def test_trajectory_reverses():
