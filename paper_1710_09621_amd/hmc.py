@@ -101,6 +101,8 @@ def main():
                     help="after --therm trajectories of --scheme, run --ntraj trajectories of each splitting (new, "
                          "old, none), every one starting from the same thermalised field")
     ap.add_argument("--therm", type=int, default=0, help="trajectories before the measured ones (reported as such)")
+    ap.add_argument("--therm-m", type=float, default=None, help="light mass of the thermalisation (default --m)")
+    ap.add_argument("--therm-mh", type=float, default=None, help="heavy mass of the thermalisation (default --mh)")
     ap.add_argument("--m", type=float, default=0.01)
     ap.add_argument("--mh", type=float, default=0.1)
     ap.add_argument("--M", type=float, default=1.0)
@@ -133,8 +135,11 @@ def main():
     prec = {"fp64": E.FP64, "fp16": E.MIXED_FP16}[args.prec]
     p = E.params(tol=1e-10, prec=prec, max_iter=50000)
 
-    def splitting(kind):
-        return levels(mpseq.actions(kind, args.m, [] if kind == "none" else [args.mh], args.M))
+    def splitting(kind, m=args.m, mh=args.mh):
+        return levels(mpseq.actions(kind, m, [] if kind == "none" else [mh], args.M))
+
+    tm = args.m if args.therm_m is None else args.therm_m
+    tmh = args.mh if args.therm_mh is None else args.therm_mh
 
     rng = np.random.Generator(np.random.PCG64(args.seed))
     out = []
@@ -144,8 +149,8 @@ def main():
         print(json.dumps(x), flush=True)
 
     for traj in range(args.therm):
-        emit(dict(phase="therm", scheme=args.scheme, traj=traj,
-                  **trajectory(ctx, U, splitting(args.scheme), rng, args.beta, args.tau, args.steps, p,
+        emit(dict(phase="therm", scheme=args.scheme, traj=traj, masses=[tm, tmh, args.M],
+                  **trajectory(ctx, U, splitting(args.scheme, tm, tmh), rng, args.beta, args.tau, args.steps, p,
                                chrono=not args.no_chrono)))
     start = U.clone()
     for scheme in (("new", "old", "none") if args.compare else (args.scheme,)):

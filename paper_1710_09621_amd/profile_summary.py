@@ -265,7 +265,8 @@ def hmc_compare(run, out_md, run_command):
              "Command (repository root, GPU box):", "", f"    {run_command}", "",
              f"beta = {lat['beta']}, (k0, k1, k2) = {tuple(lat['steps'])}, {lat['prec']} solves to 1e-10, chronological "
              f"start vectors: {lat['chrono']}. {len(therm)} thermalisation trajectories of the "
-             f"{therm[0]['scheme'] if therm else '-'} splitting (plaquette {therm[0]['plaquette'] if therm else 0:.4f} -> "
+             f"{therm[0]['scheme'] if therm else '-'} splitting with (m, m_h, M) = "
+             f"{tuple(therm[0].get('masses', [])) if therm else '-'} (plaquette {therm[0]['plaquette'] if therm else 0:.4f} -> "
              f"{therm[-1]['plaquette'] if therm else 0:.4f}); then every splitting runs {lat['ntraj']} trajectories from "
              "the same field. ‖F‖ = sqrt(sum_a F^a F^a) averaged over the links; per action the largest over its force "
              "evaluations in a trajectory (mean over the trajectories).", "",
