@@ -5,7 +5,7 @@
         [FETCH_STDOUT]
     python -m paper_1710_09621_amd.profile_summary hmc DIR RUN1.jsonl,RUN2.jsonl OUT_MD "TRACE_COMMAND" "RUN_COMMAND"
     python -m paper_1710_09621_amd.profile_summary hmc_eq RUN.jsonl OUT_MD "RUN_COMMAND"
-    python -m paper_1710_09621_amd.profile_summary hmc_compare RUN.jsonl OUT_MD "RUN_COMMAND"
+    python -m paper_1710_09621_amd.profile_summary hmc_compare RUN.jsonl OUT_MD "RUN_COMMAND" [paper]
     python -m paper_1710_09621_amd.profile_summary force DIR OUT_MD "COMMAND"
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
@@ -253,7 +253,14 @@ def force(d, out_md, command, dims=(32, 32, 32, 64), Ns=16):
     print(out_md, f"k_force {avg:.1f} us")
 
 
-def hmc_compare(run, out_md, run_command):
+# The maximum fermion forces per factor and the time per trajectory that Sec. III prints for one-flavour QCD on its
+# 24^3 x 48 ensembles at beta = 6.20 with m_q = 0.005, m_h = 0.1 (bare; 0.005 / 2.6 and 0.1 / 2.6 normalised)
+PAPER_NF1 = {"none": dict(forces=[0.0830, 0.2529], seconds=46162, acceptance=0.97),
+             "old": dict(forces=[0.0012, 0.0040, 0.0234, 0.2244], seconds=22839, acceptance=0.88),
+             "new": dict(forces=[0.0011, 0.0348, 0.2243], seconds=18346, acceptance=0.88)}
+
+
+def hmc_compare(run, out_md, run_command, paper=""):
     """The three splittings from one thermalised field (hmc.py --therm N --compare): per splitting the time, CG
     iterations, acceptance and the force magnitudes per action."""
     with open(run) as f:
@@ -276,6 +283,20 @@ def hmc_compare(run, out_md, run_command):
         acts = "; ".join(f"({a[0]}, {a[1]:+d}, {a[2]}, {a[3]}, {a[4]})" for a in sm["actions"])
         lines.append(f"| {sm['scheme']} | {acts} | {sm['mean_s']:.2f} | {sm['mean_cg']:.0f} | {sm['accepted']}/{sm['ntraj']} | "
                      f"{', '.join(f'{v:.4f}' for v in sm['force_max'])} | {sm['gauge_force0']:.3f} |")
+    if paper:
+        lines += ["", "The same quantities as printed in Sec. III for one-flavour QCD (24³×48, β = 6.20, m_q = 0.005, "
+                  "m_h = 0.1 bare, i.e. the normalised masses of this run; other hardware and volume):", "",
+                  "| splitting | largest ‖F‖ per action, Sec. III | this run | seconds per trajectory, Sec. III (ratio to new MP) "
+                  "| this run (ratio to new MP) |", "|---|---|---|---:|---:|"]
+        ours = {sm["scheme"]: sm for sm in summs}
+        for k in ("new", "old", "none"):
+            if k not in ours:
+                continue
+            pp, o = PAPER_NF1[k], ours[k]
+            lines.append(f"| {k} | {', '.join(f'{v:.4f}' for v in pp['forces'])} | "
+                         f"{', '.join(f'{v:.4f}' for v in o['force_max'])} | {pp['seconds']} "
+                         f"({pp['seconds'] / PAPER_NF1['new']['seconds']:.2f}) | {o['mean_s']:.1f} "
+                         f"({o['mean_s'] / ours['new']['mean_s']:.2f}) |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(out_md)
@@ -317,7 +338,7 @@ if __name__ == "__main__":
     elif sys.argv[1] == "force":
         force(*sys.argv[2:5])
     elif sys.argv[1] == "hmc_compare":
-        hmc_compare(*sys.argv[2:5])
+        hmc_compare(*sys.argv[2:6])
     elif sys.argv[1] == "hmc_eq":
         hmc_eq(*sys.argv[2:5])
     else:
