@@ -248,6 +248,8 @@ typedef struct {
                             point without a test */
     int chrono;          /* != 0: every force solve after an action's first in the trajectory starts from that
                             action's previous solution (kept in 2 half fields per action, allocated once) */
+    double force_tol;    /* > 0: true-residual target of the force solves between the first and the last force
+                            evaluation (which also give H and keep `solve`'s tol); 0: `solve`'s tol throughout */
 } eofa_md_params;
 typedef struct {
     double H0, H1, dH;           /* Hamiltonian at the start and the end of the trajectory */

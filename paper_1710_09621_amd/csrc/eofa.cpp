@@ -1886,11 +1886,14 @@ void md_kick(MdRun& m, int level, double h) {
     m.has[level] = true;
 }
 
-// Apply every pending kick at the current links.
-void md_flush(MdRun& m) {
+// Apply every pending kick at the current links.  last: the flush at the end of the trajectory.
+void md_flush(MdRun& m, bool last = false) {
     eofa_ctx* ctx = m.ctx;
     m.Sf_flush = 0;
     int solved = 0;
+    // the first and the last evaluations also give the actions in H: they keep the solve's tolerance
+    eofa_solve_params fp = *m.sp;
+    if (m.md->force_tol > 0 && m.info->link_updates > 0 && !last) fp.tol = m.md->force_tol;
     for (int level = 0; level < m.md->nlevels; level++) {
         if (!m.has[level]) continue;
         const double h = m.pend[level];
@@ -1907,7 +1910,7 @@ void md_flush(MdRun& m) {
             eofa_solve_info si{};
             double S = 0;
             cd* const* g = m.md->chrono ? &ctx->md_guess[2 * i] : nullptr;
-            const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, &S, m.sp, &si,
+            const eofa_status st = chiral_force_impl(ctx, a.chir, a.m3, a.m4, a.mo, a.phi, ctx->md_F, &S, &fp, &si,
                                                      g && m.have[i] ? g : nullptr, g);
             if (g) m.have[i] = true;
             m.info->cg_iters += si.iters;
@@ -2085,6 +2088,8 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
         REQUIRE(md->nlevels >= 1 && md->nlevels <= 4, EOFA_EINVAL, "nlevels must be 1 .. 4");
         REQUIRE(md->tau > 0 && std::isfinite(md->tau) && std::isfinite(md->beta), EOFA_EINVAL, "bad tau or beta");
         REQUIRE(md->metropolis_u < 1.0, EOFA_EINVAL, "metropolis_u must be < 1");
+        REQUIRE(md->force_tol >= 0 && md->force_tol < 1 && std::isfinite(md->force_tol), EOFA_EINVAL,
+                "force_tol must lie in [0, 1)");
         for (int j = 0; j < md->nlevels; j++) REQUIRE(md->steps[j] >= 1, EOFA_EINVAL, "steps must be >= 1");
         for (int j = 1; j < md->nlevels; j++)
             REQUIRE(md->steps[j - 1] % (2 * md->steps[j]) == 0, EOFA_EINVAL,
@@ -2138,7 +2143,7 @@ eofa_status eofa_md_trajectory(eofa_ctx* ctx, void* U, double* P, int nact, cons
         }
         try {
             md_integrate(m, md->nlevels - 1, md->tau);
-            md_flush(m);  // the last kicks, at U(tau)
+            md_flush(m, true);  // the last kicks, at U(tau)
         } catch (const Fail&) {  // a solve failed: hand back the starting links (P holds the partial update)
             const std::string why = ctx->err;
             HIPCHK(launch_copy(U, ctx->md_U0, sizeof(cd) * nU, ctx->st));

@@ -72,7 +72,7 @@ class MdAction(C.Structure):
 
 class MdParams(C.Structure):
     _fields_ = [("beta", C.c_double), ("tau", C.c_double), ("nlevels", C.c_int), ("steps", C.c_int * 4),
-                ("metropolis_u", C.c_double), ("chrono", C.c_int)]
+                ("metropolis_u", C.c_double), ("chrono", C.c_int), ("force_tol", C.c_double)]
 
 
 class MdInfo(C.Structure):
@@ -388,7 +388,7 @@ class Context:
         self._check(self.lib.eofa_gauge_force(self.h, _ptr(U), float(beta), _ptr(F)), "gauge_force")
         return F
 
-    def md_trajectory(self, U, P, actions, beta, tau, steps, metropolis_u=-1.0, p=None, chrono=False):
+    def md_trajectory(self, U, P, actions, beta, tau, steps, metropolis_u=-1.0, p=None, chrono=False, force_tol=0.0):
         """One molecular-dynamics trajectory, in place on U (complex128 [t][z][y][x][mu][3][3]) and P (float64
         [mu][t][z][y][x][8]), both device tensors.  actions: list of (level, chir, m3, m4, mo, phi); steps: total
         steps per level, innermost (gauge) first.  Returns the info dict."""
@@ -405,7 +405,7 @@ class Context:
             acts[i] = MdAction(int(chir), float(m3), float(m4), float(mo), int(lev), phis[i].data_ptr())
         steps = list(steps)
         md = MdParams(float(beta), float(tau), len(steps), (C.c_int * 4)(*(steps + [0] * (4 - len(steps)))),
-                      float(metropolis_u), int(bool(chrono)))
+                      float(metropolis_u), int(bool(chrono)), float(force_tol))
         self._prep_ws(p)
         info = MdInfo()
         st = self.lib.eofa_md_trajectory(self.h, _ptr(U), _ptr(P), len(actions), acts, C.byref(md), C.byref(p),

@@ -270,7 +270,8 @@ def hmc_compare(run, out_md, run_command, paper=""):
     lat = summs[0]
     lines = [f"# The splittings of Sec. III from one thermalised field: {lat['lattice']}, Ns = {lat['Ns']}", "",
              "Command (repository root, GPU box):", "", f"    {run_command}", "",
-             f"beta = {lat['beta']}, (k0, k1, k2) = {tuple(lat['steps'])}, {lat['prec']} solves to 1e-10, chronological "
+             f"beta = {lat['beta']}, (k0, k1, k2) = {tuple(lat['steps'])}, {lat['prec']} solves to 1e-10 (interior force "
+             f"solves to {lat.get('force_tol') or 1e-10:g}), chronological "
              f"start vectors: {lat['chrono']}. {len(therm)} thermalisation trajectories of the "
              f"{therm[0]['scheme'] if therm else '-'} splitting with (m, m_h, M) = "
              f"{tuple(therm[0].get('masses', [])) if therm else '-'} (plaquette {therm[0]['plaquette'] if therm else 0:.4f} -> "

@@ -232,3 +232,28 @@ def test_hmc_driver_trajectories():
     Un = Ug.cpu().numpy()
     assert np.abs(np.conj(np.swapaxes(Un, -1, -2)) @ Un - np.eye(3)).max() < 1e-12
     assert np.abs(np.linalg.det(Un) - 1).max() < 1e-12
+
+
+def test_looser_interior_force_solves():
+    """force_tol: the interior force solves stop at a looser residual while the first and last evaluations (which
+    give H) keep the tight one; the trajectory moves by about that residual and needs fewer CG iterations."""
+    from paper_1710_09621_amd import eofa as E
+    dims, Ns = (4, 4, 4, 4), 4
+    ctx, U, _ = _setup(dims, Ns, 0.5, 33)
+    acts = _fermion_case(dims, Ns, 34)
+    P = _momenta(dims, 35)
+    dev = torch.device("cuda")
+    out = []
+    for ft in (0.0, 1e-8):
+        Ug = torch.from_numpy(U.copy()).to(dev)
+        Pg = torch.from_numpy(P.copy()).to(dev)
+        info = ctx.md_trajectory(Ug, Pg, acts, 5.7, 0.5, [8, 4, 2], p=E.params(tol=1e-12), chrono=True, force_tol=ft)
+        out.append((info, Ug.cpu().numpy()))
+        print(f"  force_tol={ft}: cg {info['cg_iters']} dH {info['dH']:.9e}", flush=True)
+    (a, Ua), (b, Ub) = out
+    assert np.abs(Ua - Ub).max() < 1e-6
+    assert abs(a["dH"] - b["dH"]) < 1e-5
+    assert b["cg_iters"] < a["cg_iters"]
+    with pytest.raises(E.EofaError):
+        ctx.md_trajectory(torch.from_numpy(U.copy()).to(dev), torch.from_numpy(P.copy()).to(dev), acts, 5.7, 0.5,
+                          [8, 4, 2], force_tol=1.5)
