@@ -33,7 +33,7 @@ def levels(acts):
     return [(1 if i == len(acts) - 1 else 2,) + tuple(a) for i, a in enumerate(acts)]
 
 
-def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True, force_tol=0.0):
+def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True, force_tol=0.0, hb_err=1e-10):
     """One HMC trajectory in place on U (device links): momenta and noise from rng, the heat-bath of every
     action, the molecular dynamics and the Metropolis test.  Returns the trajectory's record."""
     import numpy as np
@@ -46,7 +46,7 @@ def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True, force_tol=0.
     for (lev, chir, m3, m4, mo) in acts:
         eta = (rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)) + 1j * rng.standard_normal((Lt, Lz, Ly, Lx, 4, 3)))
         eta *= np.sqrt(0.5)  # weight exp(-eta^dag eta)
-        phi, info = ctx.chiral_heatbath(chir, m3, m4, mo, eta, p=p)
+        phi, info = ctx.chiral_heatbath(chir, m3, m4, mo, eta, rel_err=hb_err, p=p)
         phis.append(phi)
         hb.append(info)
     torch.cuda.synchronize()
@@ -70,7 +70,7 @@ def summarize(lines, dims, Ns, scheme, acts, args):
     import numpy as np
     summary = dict(lattice="x".join(map(str, dims)), Ns=Ns, scheme=scheme, actions=[list(a) for a in acts],
                    beta=args.beta, steps=args.steps, prec=args.prec, ntraj=len(lines), chrono=not args.no_chrono,
-                   force_tol=args.force_tol,
+                   force_tol=args.force_tol, hb_err=args.hb_err,
                    accepted=sum(1 for x in lines if x["accepted"] == 1),
                    mean_s=round(sum(x["seconds"] for x in lines) / len(lines), 3),
                    mean_cg=round(sum(x["cg_iters"] for x in lines) / len(lines), 1),
@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--out", default=None, help="also write the lines to this file")
     ap.add_argument("--force-tol", type=float, default=1e-8,
                     help="residual target of the interior force solves (0: the actions' 1e-10)")
+    ap.add_argument("--hb-err", type=float, default=1e-10,
+                    help="relative error of the rational approximation of x^(-1/2) in the heat-bath")
     ap.add_argument("--no-chrono", action="store_true",
                     help="start every force solve from zero instead of the action's previous solution")
     ap.add_argument("--burn", type=int, default=0,
@@ -154,7 +156,7 @@ def main():
     for traj in range(args.therm):
         emit(dict(phase="therm", scheme=args.scheme, traj=traj, masses=[tm, tmh, args.M],
                   **trajectory(ctx, U, splitting(args.scheme, tm, tmh), rng, args.beta, args.tau, args.steps, p,
-                               chrono=not args.no_chrono, force_tol=args.force_tol)))
+                               chrono=not args.no_chrono, force_tol=args.force_tol, hb_err=args.hb_err)))
     start = U.clone()
     for scheme in (("new", "old", "none") if args.compare else (args.scheme,)):
         U.copy_(start)
@@ -163,7 +165,8 @@ def main():
         lines = []
         for traj in range(args.ntraj):
             line = dict(traj=traj, scheme=scheme, **trajectory(ctx, U, acts, rng, args.beta, args.tau, args.steps, p,
-                                                               chrono=not args.no_chrono, force_tol=args.force_tol))
+                                                               chrono=not args.no_chrono, force_tol=args.force_tol,
+                                                               hb_err=args.hb_err))
             lines.append(line)
             emit(line)
         emit(dict(summary=summarize(lines, dims, Ns, scheme, acts, args)))
