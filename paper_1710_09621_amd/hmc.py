@@ -33,7 +33,7 @@ def levels(acts):
     return [(1 if i == len(acts) - 1 else 2,) + tuple(a) for i, a in enumerate(acts)]
 
 
-def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True, force_tol=0.0, hb_err=1e-10):
+def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True, force_tol=0.0, hb_err=1e-10, metropolis=True):
     """One HMC trajectory in place on U (device links): momenta and noise from rng, the heat-bath of every
     action, the molecular dynamics and the Metropolis test.  Returns the trajectory's record."""
     import numpy as np
@@ -52,7 +52,8 @@ def trajectory(ctx, U, acts, rng, beta, tau, steps, p, chrono=True, force_tol=0.
     torch.cuda.synchronize()
     t_hb = time.perf_counter() - t0
     u = float(rng.random())
-    md = ctx.md_trajectory(U, P, [a + (phis[i],) for i, a in enumerate(acts)], beta, tau, steps, metropolis_u=u,
+    md = ctx.md_trajectory(U, P, [a + (phis[i],) for i, a in enumerate(acts)], beta, tau, steps,
+                           metropolis_u=u if metropolis else -1.0,
                            p=p, chrono=chrono, force_tol=force_tol)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -101,7 +102,10 @@ def main():
     ap.add_argument("--compare", action="store_true",
                     help="after --therm trajectories of --scheme, run --ntraj trajectories of each splitting (new, "
                          "old, none), every one starting from the same thermalised field")
+    ap.add_argument("--schemes", default="new,old,none", help="the splittings --compare runs, in order")
     ap.add_argument("--therm", type=int, default=0, help="trajectories before the measured ones (reported as such)")
+    ap.add_argument("--therm-nomet", action="store_true",
+                    help="keep the end point of every thermalisation trajectory (no Metropolis test), for rough starts")
     ap.add_argument("--therm-m", type=float, default=None, help="light mass of the thermalisation (default --m)")
     ap.add_argument("--therm-mh", type=float, default=None, help="heavy mass of the thermalisation (default --mh)")
     ap.add_argument("--m", type=float, default=0.01)
@@ -156,9 +160,10 @@ def main():
     for traj in range(args.therm):
         emit(dict(phase="therm", scheme=args.scheme, traj=traj, masses=[tm, tmh, args.M],
                   **trajectory(ctx, U, splitting(args.scheme, tm, tmh), rng, args.beta, args.tau, args.steps, p,
-                               chrono=not args.no_chrono, force_tol=args.force_tol, hb_err=args.hb_err)))
+                               chrono=not args.no_chrono, force_tol=args.force_tol, hb_err=args.hb_err,
+                               metropolis=not args.therm_nomet)))
     start = U.clone()
-    for scheme in (("new", "old", "none") if args.compare else (args.scheme,)):
+    for scheme in (tuple(args.schemes.split(",")) if args.compare else (args.scheme,)):
         U.copy_(start)
         ctx.set_gauge(U)
         acts = splitting(scheme)
