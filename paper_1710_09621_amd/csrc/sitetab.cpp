@@ -113,6 +113,8 @@ void build_half(ChirTab& t, SiteKind kind, int Ns, double m0, const double* om, 
         for (int s = 0; s < Ns; s++) t.post[s] = kappa / std::sqrt(om[s]);
         break;
     }
+    case SK_NKIND:  // not a table kind: the tables stay zero
+        break;
     }
 }
 
