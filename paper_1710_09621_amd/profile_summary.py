@@ -7,6 +7,8 @@
     python -m paper_1710_09621_amd.profile_summary hmc_eq RUN.jsonl OUT_MD "RUN_COMMAND"
     python -m paper_1710_09621_amd.profile_summary hmc_compare RUN.jsonl OUT_MD "RUN_COMMAND" [paper]
     python -m paper_1710_09621_amd.profile_summary force DIR OUT_MD "COMMAND"
+    python -m paper_1710_09621_amd.profile_summary cg_traffic FETCH_DIR WRITE_DIR FETCH_STDOUT OUT_MD "FETCH_COMMAND" \
+        "WRITE_COMMAND"
 
 trace: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run of bench.py and, for the benchmark's
 dominant kernel (the FP64 hop K1 of the schedule the bench picked), the average duration of its launches in
@@ -18,6 +20,10 @@ for k_site, which reads and writes exactly one FP64 half field; the result carri
 sources so that bench.py drops it once the kernels change.  The schedules, in launch order, come from the
 JSON lines profile_hop.py printed in the FETCH_SIZE run (FETCH_STDOUT), else from the --sched options of
 FETCH_COMMAND.
+
+cg_traffic: the same two counters for the five kernels of one FP64 CG iteration (profile_hop.py --cg N: the last N
+launches of each), scaled by the same k_site calibration, against the algorithmic bytes the library's kernel
+timing reports for each kernel (from the JSON line of the FETCH_SIZE run).
 """
 from __future__ import annotations
 
@@ -173,6 +179,66 @@ def traffic(fetch_dir, write_dir, out_json, fetch_cmd, write_cmd, fetch_stdout=N
         fo.write(text)
     res["by_schedule"] = {k: {"amplification": v[3]} for k, v in rows.items()}
     print(out_json, {k: v["amplification"] for k, v in res["by_schedule"].items()})
+
+
+CG_KERNELS = [("hop", "K1 u = A_T^-1 H_eo p"), ("schur_w", "K2 w = Dhat p, wt = A_T^-dag w, ‖w‖²"),
+              ("hop_dag", "K3 at = A_T^-dag g5 H_eo g5 wt"), ("schur_q", "K4 r -= alpha (w - H_oe at / 4), ‖r‖²"),
+              ("xp", "K5 x += alpha p, p = r + beta p")]
+
+
+def _cg_class(name):
+    """K1..K5 key of a kernel name of the FP64 CG iteration, else None."""
+    import re
+    if "k_cg_xp<double>" in name:
+        return "xp"
+    m = re.search(r"k_hop(?:_tws?)?<16, (false|true), (\d), (?:false|true), double", name)
+    if not m:
+        return None
+    return {("false", "1"): "hop", ("false", "2"): "schur_w", ("true", "1"): "hop_dag",
+            ("true", "3"): "schur_q"}.get((m.group(1), m.group(2)))
+
+
+def cg_traffic(fetch_dir, write_dir, fetch_stdout, out_md, fetch_cmd, write_cmd):
+    with open(fetch_stdout) as fo:
+        info = [json.loads(ln) for ln in fo if ln.startswith("{") and "cg_iters" in ln][-1]
+    dims, Ns, n = tuple(info["dims"]), info["Ns"], info["cg_iters"]
+    f = _per_dispatch(fetch_dir, "FETCH_SIZE")
+    w = _per_dispatch(write_dir, "WRITE_SIZE")
+    Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    half = Vh * 12 * Ns * 16
+    cal_f = [v for nm, v in f if "k_site<16, false, double>" in nm]
+    cal_w = [v for nm, v in w if "k_site<16, false, double>" in nm]
+    ff = half / (sum(cal_f) / len(cal_f) * 1024)
+    wf = half / (sum(cal_w) / len(cal_w) * 1024)
+    lines = ["# FP64 CG iteration kernels on %s, Ns = %d: measured HBM traffic" % ("x".join(map(str, dims)), Ns), "",
+             "Commands (repository root, GPU box; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "    " + fetch_cmd, "    " + write_cmd, "",
+             "Schedule %s; %d CG iterations of the benchmark step (action (+1, 0.01, 0.1, 1.0)), the last %d launches "
+             "of each kernel. Counters in KiB per dispatch, scaled by what they read for `k_site<16, false, double>` "
+             "(one FP64 half field of %d bytes read and one written): FETCH_SIZE x %.4f, WRITE_SIZE x %.4f "
+             "(calibration dispatches: %d)." % (info["schedule"], n, n, half, ff, wf, len(cal_f)), "",
+             "| kernel | algorithmic GB | read GB | written GB | measured GB | measured / algorithmic |",
+             "|---|---:|---:|---:|---:|---:|"]
+    tot = [0.0, 0.0, 0.0]
+    for key, desc in CG_KERNELS:
+        fk = [v for nm, v in f if _cg_class(nm) == key][-n:]
+        wk = [v for nm, v in w if _cg_class(nm) == key][-n:]
+        assert len(fk) == len(wk) == n, (key, len(fk), len(wk))
+        k = info["kernels"][key]
+        alg = k["bytes"] / k["launches"]
+        rd = ff * 1024 * sum(fk) / n
+        wr = wf * 1024 * sum(wk) / n
+        tot[0] += alg
+        tot[1] += rd
+        tot[2] += wr
+        lines.append("| %s | %.3f | %.3f | %.3f | %.3f | %.3f |" % (desc, alg / 1e9, rd / 1e9, wr / 1e9,
+                                                                   (rd + wr) / 1e9, (rd + wr) / alg))
+    lines.append("| one iteration | %.3f | %.3f | %.3f | %.3f | %.3f |" % (tot[0] / 1e9, tot[1] / 1e9, tot[2] / 1e9,
+                                                                          (tot[1] + tot[2]) / 1e9,
+                                                                          (tot[1] + tot[2]) / tot[0]))
+    with open(out_md, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def hmc(d, runs, out_md, command, run_command):
@@ -342,5 +408,7 @@ if __name__ == "__main__":
         hmc_compare(*sys.argv[2:6])
     elif sys.argv[1] == "hmc_eq":
         hmc_eq(*sys.argv[2:5])
+    elif sys.argv[1] == "cg_traffic":
+        cg_traffic(*sys.argv[2:8])
     else:
         raise SystemExit(__doc__)
