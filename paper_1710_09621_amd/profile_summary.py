@@ -189,7 +189,7 @@ CG_KERNELS = [("hop", "K1 u = A_T^-1 H_eo p"), ("schur_w", "K2 w = Dhat p, wt = 
 def _cg_class(name):
     """K1..K5 key of a kernel name of the FP64 CG iteration, else None."""
     import re
-    if "k_cg_xp<double>" in name:
+    if "k_cg_xp<double" in name:
         return "xp"
     m = re.search(r"k_hop(?:_tws?)?<16, (false|true), (\d), (?:false|true), double", name)
     if not m:
