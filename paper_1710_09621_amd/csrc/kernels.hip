@@ -28,6 +28,11 @@ template <typename R> __device__ __forceinline__ void st_out(cpx<R>* p, const cp
     __builtin_nontemporal_store(v.y, &p->y);
 }
 template <typename T> __device__ __forceinline__ void st_raw(T* p, const T& v) { __builtin_nontemporal_store(v, p); }
+// The epilogues' site-local inputs (aux, aux2) are read once per launch: nontemporal loads, so that they do not
+// displace the re-read neighbour spinors either.
+template <typename R> __device__ __forceinline__ cpx<R> ld_once(const cpx<R>* p) {
+    return {__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
 
 // ---- FP16 storage of a Krylov half field (EOFA_MIXED_FP16): per (cb, s) column the 12 complex
 // components as binary16 (re, im) pairs in 3 blocks of 4 (16 bytes, one load per block):
@@ -244,7 +249,7 @@ template <int NS, typename R>
 __device__ __forceinline__ void add_aux_ns(cpx<R> v[12], const cpx<R>* __restrict__ aux, R c) {
 #pragma unroll
     for (int j = 0; j < 12; j++) {
-        cpx<R> t = aux[j * NS];
+        cpx<R> t = ld_once(aux + j * NS);
         v[j].x = fma(c, t.x, v[j].x);
         v[j].y = fma(c, t.y, v[j].y);
     }
@@ -291,7 +296,7 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<R>& a, cpx<R> z[12]
         site_op<NS, false>(z, opA, s, lane);
 #pragma unroll
         for (int j = 0; j < 12; j++) {
-            cpx<R> t = a.aux[base + j * NS];
+            cpx<R> t = ld_once(a.aux + base + j * NS);
             v[j].x = fma(a.cz, z[j].x, a.caux * t.x);
             v[j].y = fma(a.cz, z[j].y, a.caux * t.y);
         }
@@ -299,7 +304,7 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs<R>& a, cpx<R> z[12]
         const R alpha = (R)a.scal[SC_ALPHA];
 #pragma unroll
         for (int j = 0; j < 12; j++) {
-            cpx<R> w = a.aux[base + j * NS], r = a.aux2[base + j * NS];
+            cpx<R> w = ld_once(a.aux + base + j * NS), r = ld_once(a.aux2 + base + j * NS);
             R qx = fma(a.cz, z[j].x, a.caux * w.x), qy = fma(a.cz, z[j].y, a.caux * w.y);
             v[j].x = fma(-alpha, qx, r.x);
             v[j].y = fma(-alpha, qy, r.y);
@@ -674,7 +679,7 @@ __device__ __forceinline__ double hop_epilogue_h(const HopArgs<R>& a, cpx<R> z[6
         if (a.aux) {
 #pragma unroll
             for (int j = 0; j < 6; j++) {
-                cpx<R> t = a.aux[base + J(j)];
+                cpx<R> t = ld_once(a.aux + base + J(j));
                 v[j].x = fma(a.caux, t.x, v[j].x);
                 v[j].y = fma(a.caux, t.y, v[j].y);
             }
@@ -684,7 +689,7 @@ __device__ __forceinline__ double hop_epilogue_h(const HopArgs<R>& a, cpx<R> z[6
         site_op_half<NS, false>(z, opA, s, lane);
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            cpx<R> t = a.aux[base + J(j)];
+            cpx<R> t = ld_once(a.aux + base + J(j));
             v[j].x = fma(a.cz, z[j].x, a.caux * t.x);
             v[j].y = fma(a.cz, z[j].y, a.caux * t.y);
         }
@@ -692,7 +697,7 @@ __device__ __forceinline__ double hop_epilogue_h(const HopArgs<R>& a, cpx<R> z[6
         const R alpha = (R)a.scal[SC_ALPHA];
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            cpx<R> w = a.aux[base + J(j)], r = a.aux2[base + J(j)];
+            cpx<R> w = ld_once(a.aux + base + J(j)), r = ld_once(a.aux2 + base + J(j));
             R qx = fma(a.cz, z[j].x, a.caux * w.x), qy = fma(a.cz, z[j].y, a.caux * w.y);
             v[j].x = fma(-alpha, qx, r.x);
             v[j].y = fma(-alpha, qy, r.y);
@@ -713,7 +718,7 @@ __device__ __forceinline__ double hop_epilogue_h(const HopArgs<R>& a, cpx<R> z[6
         if (a.aux) {
 #pragma unroll
             for (int j = 0; j < 6; j++) {
-                cpx<R> t = a.aux[base + J(j)];
+                cpx<R> t = ld_once(a.aux + base + J(j));
                 v[j].x = fma(a.caux, t.x, v[j].x);
                 v[j].y = fma(a.caux, t.y, v[j].y);
             }
