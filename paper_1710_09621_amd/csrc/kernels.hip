@@ -44,13 +44,15 @@ template <int NS> __device__ __forceinline__ const float* h_norms(const void* f,
     return (const float*)((const h8_t*)f + (size_t)3 * Vh * NS);
 }
 
-template <int NS>
+// NT: nontemporal loads (a column read once per launch)
+template <int NS, bool NT = false>
 __device__ __forceinline__ void load_h(cpx<float> p[12], const void* __restrict__ f, size_t cb, int s, int Vh) {
     const h8_t* d = (const h8_t*)f + cb * 3 * NS + s;
-    const float n = h_norms<NS>(f, Vh)[cb * NS + s];
+    const float* np = h_norms<NS>(f, Vh) + cb * NS + s;
+    const float n = NT ? __builtin_nontemporal_load(np) : *np;
 #pragma unroll
     for (int jb = 0; jb < 3; jb++) {
-        const h8_t v = d[jb * NS];
+        const h8_t v = NT ? __builtin_nontemporal_load(d + jb * NS) : d[jb * NS];
 #pragma unroll
         for (int k = 0; k < 4; k++) p[4 * jb + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
     }
@@ -76,15 +78,15 @@ __device__ __forceinline__ void store_h(void* __restrict__ f, size_t cb, int s, 
     st_raw((float*)h_norms<NS>(f, Vh) + cb * NS + s, m);
 }
 
-// 12 components of (cb, s) from a field in storage H (FP16 columns) or plain cpx<R>
-template <int NS, bool H, typename R>
+// 12 components of (cb, s) from a field in storage H (FP16 columns) or plain cpx<R>; NT: nontemporal loads
+template <int NS, bool H, bool NT = false, typename R>
 __device__ __forceinline__ void load_col(cpx<R> p[12], const void* __restrict__ f, size_t cb, int s, int Vh) {
     if constexpr (H) {
-        load_h<NS>(p, f, cb, s, Vh);
+        load_h<NS, NT>(p, f, cb, s, Vh);
     } else {
         const cpx<R>* src = (const cpx<R>*)f + cb * 12 * NS + s;
 #pragma unroll
-        for (int j = 0; j < 12; j++) p[j] = src[j * NS];
+        for (int j = 0; j < 12; j++) p[j] = NT ? ld_once(src + j * NS) : src[j * NS];
     }
 }
 
@@ -922,7 +924,7 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
         } else if constexpr (MODE == HM_SCHUR_W) {
             site_op<NS, false>(z, sOps[2 * r], s, lane);
             cpx<R> t[12];
-            load_col<NS, H>(t, a.aux[r], (size_t)cb, s, a.g.Vh);
+            load_col<NS, H, true>(t, a.aux[r], (size_t)cb, s, a.g.Vh);
 #pragma unroll
             for (int j = 0; j < 12; j++) {
                 v[j].x = fma(a.cz, z[j].x, a.caux * t[j].x);
@@ -931,11 +933,11 @@ __global__ __launch_bounds__(256, HOP_WAVES) void k_hop_mr(const HopArgsMR<R> a)
         } else {  // HM_SCHUR_Q
             const R alpha = (R)S[SC_ALPHA];
             cpx<R> w[12];
-            load_col<NS, H>(w, a.aux[r], (size_t)cb, s, a.g.Vh);
+            load_col<NS, H, true>(w, a.aux[r], (size_t)cb, s, a.g.Vh);
             const cpx<R>* aux2 = a.aux2[r] + base;
 #pragma unroll
             for (int j = 0; j < 12; j++) {
-                cpx<R> rr = aux2[j * NS];
+                cpx<R> rr = ld_once(aux2 + j * NS);
                 R qx = fma(a.cz, z[j].x, a.caux * w[j].x), qy = fma(a.cz, z[j].y, a.caux * w[j].y);
                 v[j].x = fma(-alpha, qx, rr.x);
                 v[j].y = fma(-alpha, qy, rr.y);
