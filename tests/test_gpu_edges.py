@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import ctx_and_oracle, relerr
+from gpu_common import ctx_and_oracle, rand5, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -147,3 +147,35 @@ def test_too_small_workspace_is_enomem(setup):
     ctx.set_workspace(torch.empty(need, dtype=torch.uint8, device="cuda"))
     r = ctx.hinv(_phi(lat, 48), 0.05, 1.0, p)
     assert all(i["true_rel_resid"] <= 1e-10 for i in r.info)
+
+
+def test_corrupted_network_blob_is_rejected():
+    """eofa_set_precond refuses a parameter blob of the wrong length or with a non-finite entry (EINVAL) before it
+    touches the device, and installs nothing; a learned-preconditioner solve without a network is ESTATE.  The
+    context stays usable: a valid blob installs afterwards and the solve reaches the FP64 tolerance."""
+    from paper_1710_09621_amd import eofa as E
+    print("[gpu] corrupted network blob dims=(4, 4, 4, 4) Ns=8", flush=True)
+    ctx, lat = ctx_and_oracle((4, 4, 4, 4), 8)  # a context of its own: no network installed
+    b = torch.as_tensor(rand5(lat, 51))
+
+    def learned_solve_is_estate():
+        with pytest.raises(E.EofaError) as ei:
+            ctx.solve_ht(b, 0.05, 1.0, E.params(pc=E.PC_LEARNED))
+        assert ei.value.status == E.ESTATE
+
+    learned_solve_is_estate()
+    good = np.zeros(E.CNN_NPARAM, np.float32)
+    for bad in (good[:-1], np.concatenate([good, good[:1]])):
+        with pytest.raises(E.EofaError) as ei:
+            ctx.set_precond(bad)
+        assert ei.value.status == E.EINVAL
+    for v in (np.nan, np.inf, -np.inf):
+        w = good.copy()
+        w[12345] = v
+        with pytest.raises(E.EofaError) as ei:
+            ctx.set_precond(w)
+        assert ei.value.status == E.EINVAL and "non-finite" in str(ei.value)
+    learned_solve_is_estate()  # the refused blobs left no network behind
+    ctx.set_precond(good)
+    x, info = ctx.solve_ht(b, 0.05, 1.0, E.params(tol=1e-10, pc=E.PC_LEARNED))
+    assert info["true_rel_resid"] <= 1e-10 and info["fell_back"] == 1  # a zero network gives nothing: CG finishes
