@@ -1028,8 +1028,9 @@ __global__ __launch_bounds__(256) void k_cg_xp_mr(const XpArgs<R> a, double* sca
     xp_chunk<R, NT>(a.x[r], a.p[r], a.r[r], (R)S[SC_ALPHA], (R)S[SC_BETA], n);
 }
 
-// FP16 form: x (FP32) += alpha p ; p (FP16 columns) = r (FP32) + beta p; one thread per (cb, s)
-template <int NS>
+// FP16 form: x (FP32) += alpha p ; p (FP16 columns) = r (FP32) + beta p; one thread per (cb, s).  The stores
+// are nontemporal; NT: the loads too (fields above the Infinity Cache, as in xp_chunk).
+template <int NS, bool NT>
 __global__ __launch_bounds__(256) void k_cg_xp_mr_h(const XpArgs<float> a, double* scal, int Vh) {
     const int r = blockIdx.y;
     const double* S = scal + r * SC_N;
@@ -1040,9 +1041,9 @@ __global__ __launch_bounds__(256) void k_cg_xp_mr_h(const XpArgs<float> a, doubl
         const size_t cb = t / NS;
         const int s = (int)(t % NS);
         cpx<float> p[12], x[12], q[12];
-        load_h<NS>(p, a.p[r], cb, s, Vh);
-        load_col<NS, false>(x, a.x[r], cb, s, Vh);
-        load_col<NS, false>(q, a.r[r], cb, s, Vh);
+        load_h<NS, NT>(p, a.p[r], cb, s, Vh);
+        load_col<NS, false, NT>(x, a.x[r], cb, s, Vh);
+        load_col<NS, false, NT>(q, a.r[r], cb, s, Vh);
 #pragma unroll
         for (int j = 0; j < 12; j++) {
             x[j].x = fmaf(alpha, p[j].x, x[j].x); x[j].y = fmaf(alpha, p[j].y, x[j].y);
@@ -1557,12 +1558,17 @@ hipError_t launch_cg_xp_mr_h(int Ns, int nr, cpx<float>* const* x, void* const* 
     XpArgs<float> a{};
     for (int i = 0; i < nr; i++) { a.x[i] = x[i]; a.p[i] = (cpx<float>*)p[i]; a.r[i] = r[i]; }
     const unsigned gx = (unsigned)(((size_t)Vh * Ns + 255) / 256);
+    const bool nt = (size_t)Vh * Ns * 12 * sizeof(cpx<float>) > kXpNtBytes;  // the FP32 x and r fields
+#define XPH(NS_)                                                                                                   \
+    if (nt) hipLaunchKernelGGL((k_cg_xp_mr_h<NS_, true>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh);           \
+    else hipLaunchKernelGGL((k_cg_xp_mr_h<NS_, false>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh);
     switch (Ns) {
-    case 8: hipLaunchKernelGGL((k_cg_xp_mr_h<8>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
-    case 16: hipLaunchKernelGGL((k_cg_xp_mr_h<16>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
-    case 32: hipLaunchKernelGGL((k_cg_xp_mr_h<32>), dim3(gx, nr), dim3(256), 0, st, a, scal, Vh); break;
+    case 8: XPH(8) break;
+    case 16: XPH(16) break;
+    case 32: XPH(32) break;
     default: return hipErrorInvalidValue;
     }
+#undef XPH
     hipLaunchKernelGGL(k_sync_done, dim3(1), dim3(64), 0, st, scal, nr);
     return hipGetLastError();
 }
