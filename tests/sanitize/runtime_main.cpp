@@ -1,0 +1,59 @@
+// Host driver for the library's runtime (paper_1710_09621_amd/csrc/eofa.cpp) under AddressSanitizer and
+// UndefinedBehaviorSanitizer, built host-only (the kernels become host stubs that are never launched).
+//
+// It calls the one entry point that needs no GPU, eofa_inv_sqrt_rational: Zolotarev's optimal rational
+// approximation of x^{-1/2} used by the heat-bath, with its elliptic functions (arithmetic-geometric mean and
+// descending Landen transformation). It runs for every pole count, on narrow and wide intervals, and also checks
+// the argument errors. Besides running clean it checks that the coefficients are finite and positive, and that the
+// reported error falls with the pole count and matches a dense evaluation. Exit status 0 on success.
+#include <cmath>
+#include <cstdio>
+
+#include "eofa.h"
+
+int main() {
+    int failures = 0, calls = 0;
+    auto fail = [&](const char* what, double lo, double hi, int n) {
+        if (failures < 10) std::fprintf(stderr, "FAIL %s lo=%g hi=%g n=%d\n", what, lo, hi, n);
+        failures++;
+    };
+    const double iv[][2] = {{0.45, 1.1}, {0.4545, 2.178}, {0.1, 10.0}, {1e-3, 1.0}, {0.999, 1.0}, {1.0, 1e4}};
+    for (const auto& v : iv) {
+        double prev = INFINITY;
+        for (int n = 1; n <= 8; n++) {
+            double a0 = 0, a[8], b[8], err = -1;
+            calls++;
+            if (eofa_inv_sqrt_rational(v[0], v[1], n, &a0, a, b, &err) != EOFA_OK) { fail("status", v[0], v[1], n); continue; }
+            bool ok = std::isfinite(a0) && a0 > 0 && std::isfinite(err) && err >= 0;
+            for (int l = 0; l < n; l++) ok = ok && std::isfinite(a[l]) && a[l] > 0 && std::isfinite(b[l]) && b[l] > 0;
+            if (!ok) fail("coefficients", v[0], v[1], n);
+            // the reported error is the maximum of |sqrt(x) r(x) - 1| on [lo, hi] (dense geometric grid)
+            double emax = 0;
+            for (int i = 0; i <= 20000; i++) {
+                const double x = v[0] * std::pow(v[1] / v[0], i / 20000.0);
+                double r = a0;
+                for (int l = 0; l < n; l++) r += a[l] / (x + b[l]);
+                emax = std::fmax(emax, std::fabs(std::sqrt(x) * r - 1));
+            }
+            if (!(emax <= err * 1.01 + 1e-15 && emax >= err * 0.9 - 1e-15)) fail("reported error", v[0], v[1], n);
+            if (err > 1e-14 && !(err < prev)) fail("error does not fall with n", v[0], v[1], n);
+            prev = err;
+        }
+    }
+    // argument errors: empty or reversed interval, lo <= 0, n outside [1, 8], null outputs
+    double a0, a[8], b[8], err;
+    const int bad[] = {eofa_inv_sqrt_rational(1.0, 1.0, 3, &a0, a, b, &err),
+                       eofa_inv_sqrt_rational(2.0, 1.0, 3, &a0, a, b, &err),
+                       eofa_inv_sqrt_rational(0.0, 1.0, 3, &a0, a, b, &err),
+                       eofa_inv_sqrt_rational(-1.0, 1.0, 3, &a0, a, b, &err),
+                       eofa_inv_sqrt_rational(0.5, 1.0, 0, &a0, a, b, &err),
+                       eofa_inv_sqrt_rational(0.5, 1.0, 9, &a0, a, b, &err),
+                       eofa_inv_sqrt_rational(0.5, 1.0, 3, nullptr, a, b, &err),
+                       eofa_inv_sqrt_rational(0.5, 1.0, 3, &a0, nullptr, b, &err),
+                       eofa_inv_sqrt_rational(0.5, 1.0, 3, &a0, a, nullptr, &err),
+                       eofa_inv_sqrt_rational(NAN, 1.0, 3, &a0, a, b, &err)};
+    for (int st : bad)
+        if (st != EOFA_EINVAL) fail("argument error not EINVAL", 0, 0, 0);
+    std::printf("runtime sanitizer driver: %d approximations, %d failure(s)\n", calls, failures);
+    return failures != 0;
+}

@@ -1,10 +1,14 @@
 """Host code under AddressSanitizer (with LeakSanitizer) and UndefinedBehaviorSanitizer, on the CPU.
 
-Two drivers under tests/sanitize/ are compiled with the sanitizers and run:
+Three drivers under tests/sanitize/ are compiled with the sanitizers and run:
   - oracle_main.c calls every exported function of the FP64 oracle (oracle/oracle.c), with its OpenMP loops, on
     small lattices with odd and even Ns;
   - sitetab_main.cpp builds every site-local s-operator table of the library (csrc/sitetab.cpp, host code) for
-    every supported Ns.
+    every supported Ns;
+  - runtime_main.cpp calls the runtime's host-only entry point, the heat-bath's rational approximation
+    (csrc/eofa.cpp, its elliptic functions included), for every pole count and its argument errors; eofa.cpp is
+    compiled with the sanitizers on its host code and linked before the built library, which supplies the
+    kernels.
 A sanitizer report (out-of-bounds access, use after free, leak, undefined arithmetic) fails the test; so does a
 failed check inside a driver.  GPU code is not instrumented: the library's device kernels are covered by the
 parity tests and by the bounds reasoning of each launcher, not by a sanitizer."""
@@ -56,4 +60,25 @@ def test_site_tables_under_sanitizers(tmp_path):
         "-I", csrc, "-I", os.path.join(ROOT, "include"), "-o", exe, os.path.join(SAN, "sitetab_main.cpp"),
         os.path.join(csrc, "sitetab.cpp")]
     subprocess.run(cmd, check=True, timeout=300)
+    assert "0 failure(s)" in _run(exe)
+
+
+def test_runtime_host_code_under_sanitizers(tmp_path):
+    hip = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    lib_dir = os.path.join(ROOT, "paper_1710_09621_amd")
+    if not os.path.exists(hip):
+        pytest.skip("hipcc not found")
+    if not os.path.exists(os.path.join(lib_dir, "libeofa.so")):
+        pytest.skip("libeofa.so not built")
+    csrc = os.path.join(lib_dir, "csrc")
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", csrc]
+    common = [hip, "-x", "hip", "--offload-arch=gfx950", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + HOST_SAN + inc
+    rt, main, exe = str(tmp_path / "eofa.o"), str(tmp_path / "main.o"), str(tmp_path / "runtime_san")
+    subprocess.run(common + ["-fPIC", "-c", os.path.join(csrc, "eofa.cpp"), "-o", rt], check=True, timeout=300)
+    subprocess.run(common + ["-c", os.path.join(SAN, "runtime_main.cpp"), "-o", main], check=True, timeout=300)
+    # the executable's own (instrumented) eofa.cpp takes precedence over the copy inside the library
+    subprocess.run([hip, "--offload-arch=gfx950"] + HOST_SAN[:4] + ["-o", exe, main, rt, "-L", lib_dir,
+                                                                    "-l:libeofa.so", "-Wl,-rpath," + lib_dir],
+                   check=True, timeout=300)
     assert "0 failure(s)" in _run(exe)
