@@ -5,7 +5,9 @@
 // approximation of x^{-1/2} used by the heat-bath, with its elliptic functions (arithmetic-geometric mean and
 // descending Landen transformation). It runs for every pole count, on narrow and wide intervals, and also checks
 // the argument errors. Besides running clean it checks that the coefficients are finite and positive, and that the
-// reported error falls with the pole count and matches a dense evaluation. Exit status 0 on success.
+// reported error falls with the pole count and matches a dense evaluation. It also calls eofa_create with every
+// kind of invalid argument: validation comes before any HIP call, so the refusal (EINVAL, no context, the
+// half-built context freed) runs on the host alone. Exit status 0 on success.
 #include <cmath>
 #include <cstdio>
 
@@ -54,6 +56,36 @@ int main() {
                        eofa_inv_sqrt_rational(NAN, 1.0, 3, &a0, a, b, &err)};
     for (int st : bad)
         if (st != EOFA_EINVAL) fail("argument error not EINVAL", 0, 0, 0);
-    std::printf("runtime sanitizer driver: %d approximations, %d failure(s)\n", calls, failures);
+
+    // eofa_create refuses invalid lattices and weights before it touches the device
+    // weights for Ns = 8, symmetric under s -> 7 - s except where a case breaks them
+    double om[8], om_asym[8], om_neg[8], om_nan[8];
+    for (int s = 0; s < 8; s++) {
+        const int d = s < 7 - s ? s : 7 - s;
+        om[s] = om_asym[s] = om_neg[s] = om_nan[s] = 0.5 + 0.1 * d;
+    }
+    om_asym[0] *= 1.001;
+    om_neg[3] = om_neg[4] = -0.5;
+    om_nan[2] = om_nan[5] = NAN;
+    const int good[4] = {4, 4, 4, 4}, odd[4] = {4, 3, 4, 4}, one[4] = {4, 4, 4, 0}, huge[4] = {1024, 1024, 1024, 64};
+    struct Case { const int* dims; int Ns; double m0; const double* omega; int tbc; const char* what; };
+    const Case cases[] = {{odd, 8, 1.8, om, -1, "odd extent"},      {one, 8, 1.8, om, -1, "zero extent"},
+                          {huge, 8, 1.8, om, -1, "huge lattice"},   {good, 6, 1.8, om, -1, "Ns = 6"},
+                          {good, 64, 1.8, om, -1, "Ns = 64"},       {good, 8, 0.0, om, -1, "m0 = 0"},
+                          {good, 8, 2.5, om, -1, "m0 = 2.5"},       {good, 8, 1.8, om, 0, "t_bc = 0"},
+                          {good, 8, 1.8, om_asym, -1, "omega not R5-symmetric"},
+                          {good, 8, 1.8, om_neg, -1, "omega <= 0"}, {good, 8, 1.8, om_nan, -1, "omega NaN"},
+                          {nullptr, 8, 1.8, om, -1, "null dims"},   {good, 8, 1.8, nullptr, -1, "null omega"}};
+    for (const Case& c : cases) {
+        eofa_ctx* ctx = reinterpret_cast<eofa_ctx*>(0x1);
+        const eofa_status st = eofa_create(&ctx, c.dims, c.Ns, c.m0, c.omega, c.tbc, nullptr);
+        calls++;
+        if (st != EOFA_EINVAL || ctx != nullptr) {
+            if (failures < 10) std::fprintf(stderr, "FAIL eofa_create %s: status %d\n", c.what, (int)st);
+            failures++;
+        }
+    }
+    if (eofa_create(nullptr, good, 8, 1.8, om, -1, nullptr) != EOFA_EINVAL) fail("eofa_create null out", 0, 0, 0);
+    std::printf("runtime sanitizer driver: %d calls, %d failure(s)\n", calls, failures);
     return failures != 0;
 }

@@ -81,4 +81,10 @@ def test_runtime_host_code_under_sanitizers(tmp_path):
     subprocess.run([hip, "--offload-arch=gfx950"] + HOST_SAN[:4] + ["-o", exe, main, rt, "-L", lib_dir,
                                                                     "-l:libeofa.so", "-Wl,-rpath," + lib_dir],
                    check=True, timeout=300)
-    assert "0 failure(s)" in _run(exe)
+    out = _run(exe)
+    assert "0 failure(s)" in out
+    # each refused eofa_create names its own reason, in the order of the driver's cases
+    why = [ln.split(": ", 1)[1] for ln in out.splitlines() if ln.startswith("eofa_create: ")]
+    assert why == ["every lattice extent must be even and >= 2"] * 2 + ["lattice too large"] + \
+        ["Ns must be 4, 8, 16 or 32"] * 2 + ["m0 must be in (0, 2)"] * 2 + ["t_bc must be +1 or -1"] + \
+        ["omega must be R5-symmetric"] + ["omega_s must be positive"] * 2 + ["null dims or omega"] * 2, why
